@@ -1,0 +1,160 @@
+/*
+ * rdct.h -- C-ABI of the MI355X (gfx950) round-off DCT library (librdct.so).
+ *
+ * Method: R. J. Cintra and F. M. Bayer, "A DCT Approximation for Image
+ * Compression".  An 8-bit greyscale plane is split into 8x8 blocks A (Section 3);
+ * each block is transformed by the 2-D separable transform T A T^T with
+ * T = C0 = [2 C], the element-wise round-off of twice the DCT matrix, whose
+ * entries are 0 and +-1 (Section 2).  The orthogonalising diagonal S (Section 2,
+ * S = sqrt((C0 C0^T)^-1) = diag(1/sqrt(g)), g = (8,6,4,6,8,6,4,6)) is never
+ * applied to pixels: it is folded into the step that follows the transform,
+ * either the retention of the first r zig-zag coefficients (Section 3) or a
+ * quantisation table (Section 2, "merged into the quantization step").  The
+ * inverse runs through the transpose, since C_orth = S C0 is orthogonal
+ * (Section 2), and the result is scored by SSE / MSE / PSNR (Section 3).
+ *
+ * Conventions for every entry point
+ *  - Buffer pointers are DEVICE pointers owned by the caller unless a comment
+ *    says "host".  The library keeps no reference after the call returns,
+ *    except for the plan and server objects, which document their own.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    compute call is asynchronous on it: arguments are validated synchronously,
+ *    before any launch; faults inside kernels surface at the caller's next
+ *    synchronisation of the stream.
+ *  - Hot-path calls (forward, inverse, compress_eval, batch_run) allocate no
+ *    memory.  Plan and server creation allocate and say so.
+ *  - Planes are W x H uint8 with a row pitch in bytes >= W.  Sides that are not
+ *    multiples of 8 are padded by replicating the last row / column; metrics
+ *    cover only the plane's own pixels.
+ *  - Coefficients are block-major: block (by, bx) (raster order over
+ *    ceil(H/8) x ceil(W/8) blocks) holds 64 consecutive values in natural order
+ *    k * 8 + l, k = vertical and l = horizontal frequency.
+ *  - Zig-zag order is the JPEG sequence starting (0,0), (0,1), (1,0), (2,0), ...
+ *  - Return value: RDCT_OK or an error code; no global error state.
+ */
+#ifndef RDCT_H_
+#define RDCT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RDCT_OK = 0,
+  RDCT_ERR_INVALID_ARG = 1, /* null pointer, bad size/pitch/r/quality/table, bad enum */
+  RDCT_ERR_UNSUPPORTED = 2, /* valid but not provided (see each call) */
+  RDCT_ERR_HIP = 3,         /* a HIP runtime call or launch failed */
+  RDCT_ERR_NO_MEMORY = 4,   /* plan / server creation could not allocate */
+  RDCT_ERR_BUDGET = 5,      /* server: request larger than the whole device budget */
+  RDCT_ERR_NOT_FOUND = 6,   /* server: unknown ticket */
+  RDCT_ERR_BUSY = 7         /* server: queue full (non-blocking submit) */
+} rdct_status_t;
+
+/* Element type of a coefficient buffer. */
+typedef enum {
+  RDCT_COEF_I32 = 0, /* int32: integer Y = C0 A C0^T, or quantised q          */
+  RDCT_COEF_I16 = 1, /* int16: same values; exact since |Y| <= 16320          */
+  RDCT_COEF_F32 = 2  /* float: scaled C_orth coefficients Z = S Y S           */
+} rdct_coef_t;
+
+/* What follows the transform. */
+typedef enum {
+  RDCT_SEL_NONE = 0,   /* keep all 64 coefficients                                   */
+  RDCT_SEL_ZIGZAG = 1, /* keep the first r zig-zag coefficients, zero the rest (Sec. 3) */
+  RDCT_SEL_QUANT = 2   /* q = round(Z / Q), halves away from zero, decided exactly     */
+} rdct_sel_mode_t;
+
+typedef struct {
+  int32_t mode;            /* rdct_sel_mode_t                                          */
+  int32_t r;               /* ZIGZAG: coefficients kept, 1..64 (the paper uses 1..45)  */
+  int32_t quality;         /* QUANT: 1..100, IJG scaling of the JPEG luminance table   */
+  int32_t level_shift;     /* 0..255 subtracted from every pixel before the transform
+                              and added back after the inverse (JPEG uses 128)         */
+  const uint16_t* qtable;  /* QUANT: optional HOST pointer to 64 entries (1..255),
+                              natural order; NULL = derive from `quality`              */
+} rdct_select_t;
+
+/* ------------------------------------------------------------------------- */
+/* Core path                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Forward transform of one plane (Section 3: T A T^T on every 8x8 sub-block,
+ * T = C0; 22 additions per 8-point pass, Section 2 / Table 1).
+ *   src        plane, `height` rows of `src_pitch` bytes (>= width).
+ *   sel        host pointer.  NONE: coef = Y.  ZIGZAG: Y (I32/I16) or Z (F32)
+ *              with positions of zig-zag rank >= r set to 0.  QUANT: q (I32/I16).
+ *   coef       ceil(H/8) * ceil(W/8) * 64 elements of `coef_type`.
+ *   F32 output is fl32 of the exact s_k s_l Y_kl (error <= 3.1e-5).
+ * Errors: INVALID_ARG (nulls, sizes <= 0, pitch < width, r or quality out of
+ * range, F32 with QUANT), HIP.
+ */
+rdct_status_t rdct_forward(const uint8_t* src, int32_t width, int32_t height,
+                           int64_t src_pitch, const rdct_select_t* sel,
+                           void* coef, rdct_coef_t coef_type, void* stream);
+
+/*
+ * Inverse transform (Section 3 "inverse procedure"; C_orth^-1 = C_orth^T,
+ * Section 2) of block-major coefficients back to a float plane.
+ *   coef_type I32/I16 with NONE or ZIGZAG: integer Y, positions of rank >= r
+ *     ignored; A' = C0^T D' Y D' C0 / 576 (D' = diag(24/g)), exact integer
+ *     numerator, one rounding to float.
+ *   coef_type F32 with NONE or ZIGZAG: Z; A' = C_orth^T Z C_orth in float64.
+ *   coef_type I32/I16 with QUANT: q; A' = C_orth^T (q . Q) C_orth in float64.
+ *   `level_shift` is added back.  dst: height rows of dst_pitch floats.
+ * Errors: INVALID_ARG, HIP.
+ */
+rdct_status_t rdct_inverse(const void* coef, rdct_coef_t coef_type,
+                           int32_t width, int32_t height, const rdct_select_t* sel,
+                           float* dst, int64_t dst_pitch, void* stream);
+
+/*
+ * Fused compress-and-evaluate (Section 3: transform, keep r or quantise,
+ * inverse, squared error) in one launch.
+ *   sel->mode ZIGZAG: r_count >= 1 values r = sel->r .. sel->r + r_count - 1
+ *     (all <= 64) are scored; sse_out[i] = sum over the plane of (576 A - R)^2
+ *     for r = sel->r + i, exact, in units of 1/576^2 (SSE = sse_out / 331776).
+ *     r_count > 1 needs width and height to be multiples of 8 (else
+ *     UNSUPPORTED); it uses the identity sum (576A - R)^2 = 576 sum over the
+ *     dropped positions of d'_k d'_l Y_kl^2, which holds because C_orth is
+ *     orthogonal.
+ *   sel->mode QUANT: r_count must be 1; sse_out[0] = sum over blocks of
+ *     round(2^20 * block SSE), the block SSE taken in float64 (SSE =
+ *     sse_out / 2^20).
+ *   sel->mode NONE: as ZIGZAG with r = 64, r_count = 1.
+ *   coef_out   optional (NULL = not written): the coefficients at r = sel->r
+ *              (ZIGZAG: masked Y or Z; QUANT: q).
+ *   recon_out  optional float plane at r = sel->r (same as rdct_inverse would
+ *              give on coef_out), recon_pitch floats per row.
+ *   sse_out    device, r_count uint64 entries, overwritten.
+ * Planes of up to 6,000,000 blocks are accepted (the uint64 sums cannot wrap).
+ */
+rdct_status_t rdct_compress_eval(const uint8_t* src, int32_t width, int32_t height,
+                                 int64_t src_pitch, const rdct_select_t* sel,
+                                 int32_t r_count, void* coef_out, rdct_coef_t coef_type,
+                                 float* recon_out, int64_t recon_pitch,
+                                 uint64_t* sse_out, void* stream);
+
+/* Units of sse_out for a selection mode: 1/576^2 (NONE, ZIGZAG) or 2^-20 (QUANT). */
+double rdct_sse_unit(int32_t mode);
+
+/* PSNR in dB of a plane from its sse_out value: 10 log10(255^2 / MSE),
+   MSE = sse_out * rdct_sse_unit(mode) / (width * height); +inf when 0. */
+double rdct_psnr(uint64_t sse, int32_t mode, int32_t width, int32_t height);
+
+/* Number of 8x8 blocks of a plane: ceil(h/8) * ceil(w/8). */
+int64_t rdct_num_blocks(int32_t width, int32_t height);
+
+const char* rdct_status_string(rdct_status_t status);
+
+/* Library version string and the GPU architecture it was built for. */
+const char* rdct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDCT_H_ */

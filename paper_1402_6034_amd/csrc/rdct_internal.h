@@ -1,0 +1,89 @@
+// Internal host/device interface of librdct: argument blocks shared by the C-ABI
+// front end, the batch planner and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rdct {
+
+// One plane as the kernels see it.
+struct Plane {
+  const uint8_t* src;
+  int64_t pitch;        // bytes per source row
+  int32_t width, height;
+  int32_t nbx, nby;     // blocks per row / column
+  int32_t nblocks;      // nbx * nby
+  int32_t aligned8;     // src and pitch are multiples of 8 bytes
+  void* coef;           // block-major coefficients (nullable)
+  float* recon;         // reconstruction (nullable)
+  int64_t rpitch;       // floats per reconstruction row
+  uint64_t* sse;        // accumulators (nullable)
+  int32_t r;            // first retained count (zig-zag), 1..64
+  uint64_t keep;        // bit kl set when natural position kl has zig-zag rank < r
+  int32_t r_count;      // number of r values scored (sweep)
+  int32_t shift;        // level shift
+  int32_t table;        // index of the quantisation constants (batch)
+};
+
+// Per-table constants of the quantisation path and the scaled-coefficient paths.
+//  qm[kl]  rational positions (g_k == g_l): two floats, lo = 1/(c Q), hi =
+//          (c Q + 1/2) / (2 c Q), c = g_k; irrational positions: the float64
+//          bits of 1 / (Q sqrt(g_k g_l)).
+//  dq[kl]  Q sqrt(1/(g_k g_l)) in float64 (dequantise and scale in one factor).
+//  qi[kl]  Q itself (integer), for the coefficient-domain error z - q Q.
+struct QuantConsts {
+  uint64_t qm[64];
+  double dq[64];
+  int32_t qi[64];
+};
+
+// Scale factors s_k s_l = 1 / sqrt(g_k g_l) in float64.
+struct ScaleConsts {
+  double ss[64];
+};
+
+enum SelKind { SEL_ZZ = 0, SEL_Q = 1 };
+enum CoefKind { CO_NONE = 0, CO_I32 = 1, CO_I16 = 2, CO_F32 = 3 };
+// EV_SPATIAL: squared error from the reconstruction, pixel by pixel.
+// EV_SWEEP:   retention errors for r .. r + r_count - 1 from coefficient energies.
+// EV_COEF:    quantisation error ||Z - q Q||^2 in the coefficient domain (equal to
+//             the pixel-domain error because C_orth is orthogonal); planes made of
+//             whole blocks only.
+enum EvalKind { EV_NONE = 0, EV_SPATIAL = 1, EV_SWEEP = 2, EV_COEF = 3 };
+enum InvKind { INV_INT_I32 = 0, INV_INT_I16 = 1, INV_F32 = 2, INV_Q_I32 = 3, INV_Q_I16 = 4 };
+
+// Work item of the persistent batch kernel: `count` (<= 128) consecutive blocks
+// of plane `plane` starting at block `t0`.
+struct WorkItem {
+  int32_t plane;
+  int32_t t0;
+};
+
+// Launch geometry choices (tuned per shape class).
+struct Geometry {
+  int32_t waves_per_wg;   // 1, 2, 4, 8
+  int32_t grid_per_cu;    // persistent kernel: workgroups per CU
+};
+
+void fill_quant_consts(const uint16_t q[64], QuantConsts* out);
+void fill_scale_consts(ScaleConsts* out);
+uint64_t keep_bits(int r);
+
+hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
+                        const QuantConsts& qc, const ScaleConsts& sc, int waves_per_wg,
+                        hipStream_t stream);
+hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height,
+                          int32_t r, int32_t shift, float* dst, int64_t dpitch,
+                          const QuantConsts& qc, const ScaleConsts& sc, hipStream_t stream);
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t stream);
+
+// Persistent batch launch over a work list.  `planes` and `tables` are device
+// arrays; `items` has n_items entries.
+hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
+                        const QuantConsts* tables, const ScaleConsts* sc_dev,
+                        const WorkItem* items, int32_t n_items, int32_t grid,
+                        int32_t waves_per_wg, hipStream_t stream);
+
+int device_cu_count();
+
+}  // namespace rdct

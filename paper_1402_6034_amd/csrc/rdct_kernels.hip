@@ -1,0 +1,765 @@
+// HIP kernels of the round-off DCT hot path for gfx950 (CDNA4, wave64).
+//
+// Method (Cintra & Bayer): every 8x8 block A of a plane is mapped to
+// Y = C0 A C0^T with C0 = [2 C] (entries 0, +-1), using an addition-only flow
+// graph of 22 additions per 8-point pass (Section 2, Fig. 1, Table 1); the
+// diagonal orthogonaliser S is folded into the zig-zag retention or the
+// quantisation that follows (Sections 2-3); the inverse runs through C0^T since
+// C_orth = S C0 is orthogonal (Section 2); the error is scored by SSE (Section 3).
+//
+// Mapping to the hardware.  The transform has no dense contraction (an 8-point
+// pass is 22 integer additions), so nothing here uses MFMA.  The kernels are
+// streaming and HBM-bound: each wave owns a chunk of 128 consecutive blocks in
+// raster order; lane j transforms blocks t0 + j and t0 + 64 + j at once, packed
+// as the low and high halves of 16-bit pairs (v_pk_add/sub_u16), which is exact
+// because |Y| <= 16320.  Row loads are 8 bytes per lane and consecutive lanes
+// read consecutive blocks, so one load instruction covers 512 contiguous bytes
+// of an image row.  Both passes stay in registers (the transpose between the
+// row and the column pass is free: a lane holds whole blocks).
+#include "rdct_internal.h"
+#include "rdct_tables.h"
+
+#include <utility>
+
+namespace rdct {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__constant__ ZigZag c_zz = make_zigzag();
+
+__device__ __forceinline__ s16x2 as_pair(uint32_t u) { return __builtin_bit_cast(s16x2, u); }
+
+// ---------------------------------------------------------------------------
+// Addition-only flow graphs for C0 and C0^T (22 additions each).
+// Forward: mirrored sums a_i = x_i + x_{7-i} feed the even outputs, mirrored
+// differences b_i = x_i - x_{7-i} feed the odd outputs.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void c0_forward(T (&x)[8]) {
+  const T a0 = x[0] + x[7], a1 = x[1] + x[6], a2 = x[2] + x[5], a3 = x[3] + x[4];
+  const T b0 = x[0] - x[7], b1 = x[1] - x[6], b2 = x[2] - x[5], b3 = x[3] - x[4];
+  const T p = a0 + a3, q = a1 + a2;
+  x[0] = p + q;
+  x[4] = p - q;
+  x[2] = a0 - a3;
+  x[6] = a2 - a1;
+  x[1] = b0 + (b1 + b2);
+  x[3] = b0 - (b2 + b3);
+  x[5] = (b0 + b3) - b1;
+  x[7] = b2 - (b1 + b3);
+}
+
+// Transposed graph: x = C0^T X.
+template <typename T>
+__device__ __forceinline__ void c0_transpose(T (&X)[8]) {
+  const T p = X[0] + X[4], m = X[0] - X[4];
+  const T a0 = p + X[2], a3 = p - X[2], a1 = m - X[6], a2 = m + X[6];
+  const T b0 = X[1] + (X[3] + X[5]);
+  const T b1 = X[1] - (X[5] + X[7]);
+  const T b2 = (X[1] + X[7]) - X[3];
+  const T b3 = X[5] - (X[3] + X[7]);
+  X[0] = a0 + b0;
+  X[7] = a0 - b0;
+  X[1] = a1 + b1;
+  X[6] = a1 - b1;
+  X[2] = a2 + b2;
+  X[5] = a2 - b2;
+  X[3] = a3 + b3;
+  X[4] = a3 - b3;
+}
+
+// Separable 2-D pass on an 8x8 register array: rows first, then columns.
+template <typename T, bool FWD>
+__device__ __forceinline__ void pass2d(T (&v)[8][8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if constexpr (FWD) c0_forward(v[i]); else c0_transpose(v[i]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    T c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = v[i][j];
+    if constexpr (FWD) c0_forward(c); else c0_transpose(c);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i][j] = c[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact quantiser: q = round(s_k s_l Y / Q), halves away from zero.
+// Rational positions (s_k s_l = 1/c): |q| = floor((2|Y| + cQ + 1/2) / (2cQ)),
+// one float FMA whose rounding error stays below the half-step margin 1/(4cQ).
+// Irrational positions (no exact ties): float64 FMA Y * m +- 1/2, whose error is
+// far below the distance of any Y / (Q sqrt(g_k g_l)) from a half-integer.
+// ---------------------------------------------------------------------------
+template <int KL>
+__device__ __forceinline__ int quantize(int y, uint64_t qm) {
+  constexpr int k = KL >> 3, l = KL & 7;
+  if constexpr (rational_pos(k, l)) {
+    const float a = __uint_as_float((uint32_t)qm);
+    const float b = __uint_as_float((uint32_t)(qm >> 32));
+    const float yf = (float)y;
+    const float t = __builtin_fmaf(__builtin_fabsf(yf), a, b);
+    return (int)__builtin_copysignf(t, yf);
+  } else {
+    const double m = __longlong_as_double((long long)qm);
+    const double yd = (double)y;
+    return (int)__builtin_fma(yd, m, __builtin_copysign(0.5, yd));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block loads (8 rows x 8 bytes), edge-replicating partial blocks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_block(const Plane& P, int t, bool valid, uint32_t (&w)[16],
+                                           int& x0, int& y0) {
+  if (!valid) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = 0;
+    x0 = 0;
+    y0 = 0;
+    return;
+  }
+  const int by = t / P.nbx;
+  const int bx = t - by * P.nbx;
+  x0 = bx * 8;
+  y0 = by * 8;
+  if (P.aligned8 && x0 + 8 <= P.width && y0 + 8 <= P.height) {
+    const uint8_t* base = P.src + (int64_t)y0 * P.pitch + x0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint2 r = *reinterpret_cast<const uint2*>(base + (int64_t)i * P.pitch);
+      w[2 * i] = r.x;
+      w[2 * i + 1] = r.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int y = min(y0 + i, P.height - 1);
+      const uint8_t* row = P.src + (int64_t)y * P.pitch;
+      uint32_t d0 = 0, d1 = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        d0 |= (uint32_t)row[min(x0 + j, P.width - 1)] << (8 * j);
+        d1 |= (uint32_t)row[min(x0 + 4 + j, P.width - 1)] << (8 * j);
+      }
+      w[2 * i] = d0;
+      w[2 * i + 1] = d1;
+    }
+  }
+}
+
+__device__ __forceinline__ int pixel(const uint32_t (&w)[16], int i, int j) {
+  return (int)((w[2 * i + (j >> 2)] >> (8 * (j & 3))) & 0xffu);
+}
+
+// Pack byte j of two row dwords into a (lo block, hi block) 16-bit pair.
+template <int J>
+__device__ __forceinline__ s16x2 unpack_pair(uint32_t lo, uint32_t hi) {
+  constexpr uint32_t sel = 0x0c000c00u | ((uint32_t)(4 + J) << 16) | (uint32_t)J;
+  return as_pair(__builtin_amdgcn_perm(hi, lo, sel));
+}
+
+__device__ __forceinline__ void forward_pair(const uint32_t (&al)[16], const uint32_t (&ah)[16],
+                                             int shift, s16x2 (&v)[8][8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    v[i][0] = unpack_pair<0>(al[2 * i], ah[2 * i]);
+    v[i][1] = unpack_pair<1>(al[2 * i], ah[2 * i]);
+    v[i][2] = unpack_pair<2>(al[2 * i], ah[2 * i]);
+    v[i][3] = unpack_pair<3>(al[2 * i], ah[2 * i]);
+    v[i][4] = unpack_pair<0>(al[2 * i + 1], ah[2 * i + 1]);
+    v[i][5] = unpack_pair<1>(al[2 * i + 1], ah[2 * i + 1]);
+    v[i][6] = unpack_pair<2>(al[2 * i + 1], ah[2 * i + 1]);
+    v[i][7] = unpack_pair<3>(al[2 * i + 1], ah[2 * i + 1]);
+  }
+  pass2d<s16x2, true>(v);
+  // A level shift only moves the DC term: rows 1..7 of C0 sum to zero and the
+  // DC gain of C0 (x) C0 is 64.
+  const short dc = (short)(64 * shift);
+  v[0][0] -= (s16x2){dc, dc};
+}
+
+// Signed 16-bit half h (0 = low block, 1 = high block) of a packed pair.
+__device__ __forceinline__ int half(s16x2 v, int h) {
+  return __builtin_amdgcn_sbfe((int)__builtin_bit_cast(uint32_t, v), 16 * h, 16);
+}
+
+// ---------------------------------------------------------------------------
+// Stores of one block's coefficients (64 values, 16-byte vector stores).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_i32(int32_t* out, const s16x2 (&v)[8][8], uint64_t keep,
+                                          int h) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int e[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) e[l] = ((keep >> (k * 8 + l)) & 1) ? half(v[k][l], h) : 0;
+    reinterpret_cast<int4*>(out)[2 * k] = make_int4(e[0], e[1], e[2], e[3]);
+    reinterpret_cast<int4*>(out)[2 * k + 1] = make_int4(e[4], e[5], e[6], e[7]);
+  }
+}
+
+__device__ __forceinline__ void store_i16(int16_t* out, const s16x2 (&v)[8][8], uint64_t keep,
+                                          int h) {
+  // Byte selectors of v_perm_b32 that gather the 16-bit half h of two pairs.
+  const uint32_t sel = h ? 0x07060302u : 0x05040100u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint32_t d[4];
+#pragma unroll
+    for (int l = 0; l < 8; l += 2) {
+      const uint32_t m0 = ((keep >> (k * 8 + l)) & 1) ? 0xffffffffu : 0u;
+      const uint32_t m1 = ((keep >> (k * 8 + l + 1)) & 1) ? 0xffffffffu : 0u;
+      const uint32_t u0 = __builtin_bit_cast(uint32_t, v[k][l]) & m0;
+      const uint32_t u1 = __builtin_bit_cast(uint32_t, v[k][l + 1]) & m1;
+      d[l >> 1] = __builtin_amdgcn_perm(u1, u0, sel);
+    }
+    reinterpret_cast<uint4*>(out)[k] = make_uint4(d[0], d[1], d[2], d[3]);
+  }
+}
+
+__device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], uint64_t keep,
+                                          const ScaleConsts& sc, int h) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    float e[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      e[l] = ((keep >> (k * 8 + l)) & 1) ? (float)((double)half(v[k][l], h) * sc.ss[k * 8 + l])
+                                         : 0.0f;
+    reinterpret_cast<float4*>(out)[2 * k] = make_float4(e[0], e[1], e[2], e[3]);
+    reinterpret_cast<float4*>(out)[2 * k + 1] = make_float4(e[4], e[5], e[6], e[7]);
+  }
+}
+
+// Store one reconstructed row of 8 pixels (clipped to the plane).
+__device__ __forceinline__ void store_row(const Plane& P, int x0, int y, const float (&px)[8]) {
+  if (y >= P.height) return;
+  float* row = P.recon + (int64_t)y * P.rpitch + x0;
+  if (x0 + 8 <= P.width && ((reinterpret_cast<uintptr_t>(row) & 15u) == 0)) {
+    reinterpret_cast<float4*>(row)[0] = make_float4(px[0], px[1], px[2], px[3]);
+    reinterpret_cast<float4*>(row)[1] = make_float4(px[4], px[5], px[6], px[7]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (x0 + j < P.width) row[j] = px[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of one block of the pair + reconstruction + squared error.
+// Retention: R = C0^T (D' (M . Y) D') C0 in int32 (|R| <= 576 * 2040), A' = R/576.
+// Returns the block's exact sum of (576 (A - shift) - R)^2 over its own pixels.
+// ---------------------------------------------------------------------------
+template <bool RECON, bool SSE>
+__device__ __forceinline__ uint64_t retention_inverse(const Plane& P, const s16x2 (&v)[8][8],
+                                                      uint64_t keep, const uint32_t (&a)[16],
+                                                      int x0, int y0, int h) {
+  int w[8][8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      w[k][l] = ((keep >> (k * 8 + l)) & 1) ? half(v[k][l], h) * (kDp[k] * kDp[l]) : 0;
+  pass2d<int, false>(w);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if constexpr (RECON) {
+      float px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        px[j] = (float)__builtin_fma((double)w[i][j], 1.0 / 576.0, (double)P.shift);
+      store_row(P, x0, y0 + i, px);
+    }
+    if constexpr (SSE) {
+      const bool row_ok = y0 + i < P.height;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = 576 * (pixel(a, i, j) - P.shift) - w[i][j];
+        const double ed = (row_ok && x0 + j < P.width) ? (double)e : 0.0;
+        acc = __builtin_fma(ed, ed, acc);
+      }
+    }
+  }
+  return (uint64_t)acc;  // exact: < 2^53 per block
+}
+
+// Quantise row K of block h of the pair, store it, and (RECON) dequantise it into
+// the float64 inverse input; (ERR) accumulate the coefficient-domain error.
+template <int K, int CO, bool RECON, bool ERR, int... L>
+__device__ __forceinline__ void quant_row(const s16x2 (&row)[8], int h, const QuantConsts& qc,
+                                          const ScaleConsts& sc, void* coef, int64_t t,
+                                          double (&w)[8][8], double& err,
+                                          std::integer_sequence<int, L...>) {
+  int q[8];
+  auto one = [&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    constexpr int kl = K * 8 + l;
+    const int y = half(row[l], h);
+    const int qq = quantize<kl>(y, qc.qm[kl]);
+    q[l] = qq;
+    if constexpr (ERR) {
+      // z - q Q with z = s_k s_l Y: one rounding (FMA) per coefficient.
+      const double d = __builtin_fma((double)y, sc.ss[kl], -(double)(qq * qc.qi[kl]));
+      err = __builtin_fma(d, d, err);
+    }
+    if constexpr (RECON) w[K][l] = (double)qq * qc.dq[kl];
+  };
+  (one(std::integral_constant<int, L>{}), ...);
+  if constexpr (CO == CO_I32) {
+    int4* out = reinterpret_cast<int4*>(reinterpret_cast<int32_t*>(coef) + t * 64 + K * 8);
+    out[0] = make_int4(q[0], q[1], q[2], q[3]);
+    out[1] = make_int4(q[4], q[5], q[6], q[7]);
+  } else if constexpr (CO == CO_I16) {
+    uint32_t d[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      d[m] = ((uint32_t)q[2 * m] & 0xffffu) | ((uint32_t)q[2 * m + 1] << 16);
+    *reinterpret_cast<uint4*>(reinterpret_cast<int16_t*>(coef) + t * 64 + K * 8) =
+        make_uint4(d[0], d[1], d[2], d[3]);
+  }
+}
+
+template <int CO, bool RECON, bool ERR, int... K>
+__device__ __forceinline__ void quant_rows(const s16x2 (&v)[8][8], int h, const QuantConsts& qc,
+                                           const ScaleConsts& sc, void* coef, int64_t t,
+                                           double (&w)[8][8], double& err,
+                                           std::integer_sequence<int, K...>) {
+  (quant_row<K, CO, RECON, ERR>(v[K], h, qc, sc, coef, t, w, err,
+                                std::make_integer_sequence<int, 8>{}), ...);
+}
+
+// Quantisation path for block h of the pair: q = round(z / Q) exactly, stored as
+// it is produced; W = q Q s_k s_l in float64, A' = C0^T W C0 + shift.
+// Returns round(2^20 * block SSE): from ||Z - q Q||^2 (EV_COEF) or pixel by
+// pixel over the block's own pixels (EV_SPATIAL).
+template <int CO, bool RECON, int EV>
+__device__ __forceinline__ uint64_t quant_block(const Plane& P, const s16x2 (&v)[8][8], int h,
+                                                const QuantConsts& qc, const ScaleConsts& sc,
+                                                int64_t t, const uint32_t (&a)[16], int x0,
+                                                int y0) {
+  constexpr bool ERR = (EV == EV_COEF);
+  constexpr bool INV = RECON || (EV == EV_SPATIAL);
+  double w[8][8];
+  double err = 0.0;
+  quant_rows<CO, INV, ERR>(v, h, qc, sc, P.coef, t, w, err, std::make_integer_sequence<int, 8>{});
+  if constexpr (INV) {
+    pass2d<double, false>(w);
+    const double sh = (double)P.shift;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (RECON) {
+        float px[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) px[j] = (float)(w[i][j] + sh);
+        store_row(P, x0, y0 + i, px);
+      }
+      if constexpr (EV == EV_SPATIAL) {
+        const bool row_ok = y0 + i < P.height;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double e = (double)pixel(a, i, j) - (w[i][j] + sh);
+          const double ed = (row_ok && x0 + j < P.width) ? e : 0.0;
+          err = __builtin_fma(ed, ed, err);
+        }
+      }
+    }
+  }
+  return (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t s) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// One wave, one chunk of 128 blocks.
+// ---------------------------------------------------------------------------
+template <int SEL, int CO, bool RECON, int EV>
+__device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& qc,
+                                            const ScaleConsts& sc, int t0, int lane,
+                                            uint32_t* lds_wave) {
+  const int tl = t0 + lane, th = t0 + 64 + lane;
+  const bool vl = tl < P.nblocks, vh = th < P.nblocks;
+  uint32_t al[16], ah[16];
+  int xl, yl, xh, yh;
+  load_block(P, tl, vl, al, xl, yl);
+  load_block(P, th, vh, ah, xh, yh);
+
+  s16x2 v[8][8];
+  forward_pair(al, ah, P.shift, v);
+
+  if constexpr (SEL == SEL_Q) {
+    uint64_t s = 0;
+    // One block of the pair at a time keeps a single 8x8 inverse live.
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      if (!(h ? vh : vl)) continue;
+      uint32_t a[16];
+      if constexpr (EV == EV_SPATIAL) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
+      }
+      s += quant_block<CO, RECON, EV>(P, v, h, qc, sc, h ? th : tl, a, h ? xh : xl, h ? yh : yl);
+    }
+    if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
+      s = wave_sum_u64(s);
+      if (lane == 0 && s != 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.sse),
+                                         (unsigned long long)s);
+    }
+    return;
+  } else {
+  const uint64_t keep = P.keep;
+  if constexpr (CO != CO_NONE) {
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int t = h ? th : tl;
+      if (!(h ? vh : vl)) continue;
+      if constexpr (CO == CO_I32)
+        store_i32(reinterpret_cast<int32_t*>(P.coef) + (int64_t)t * 64, v, keep, h);
+      else if constexpr (CO == CO_I16)
+        store_i16(reinterpret_cast<int16_t*>(P.coef) + (int64_t)t * 64, v, keep, h);
+      else
+        store_f32(reinterpret_cast<float*>(P.coef) + (int64_t)t * 64, v, keep, sc, h);
+    }
+  }
+
+  constexpr bool SP = (EV == EV_SPATIAL);
+  if constexpr (RECON || SP) {
+    uint64_t s = 0;
+    // One block at a time keeps a single 8x8 inverse live in registers.
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      if (!(h ? vh : vl)) continue;
+      uint32_t a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
+      s += retention_inverse<RECON, SP>(P, v, keep, a, h ? xh : xl, h ? yh : yl, h);
+    }
+    if constexpr (SP) {
+      s = wave_sum_u64(s);
+      if (lane == 0 && s != 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.sse),
+                                         (unsigned long long)s);
+    }
+  }
+
+  if constexpr (EV == EV_SWEEP) {
+    // Per-position energies of the pair, transposed through LDS so that lane rho
+    // sums the position of zig-zag rank rho over the chunk.
+#pragma unroll
+    for (int kl = 0; kl < 64; ++kl) {
+      const int y0v = vl ? (int)v[kl >> 3][kl & 7].x : 0;
+      const int y1v = vh ? (int)v[kl >> 3][kl & 7].y : 0;
+      lds_wave[lane * 65 + kl] = (uint32_t)(y0v * y0v) + (uint32_t)(y1v * y1v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int pos = c_zz.order[lane];
+    uint64_t e = 0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) e += lds_wave[j * 65 + pos];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Weighted energy d'_k d'_l sum Y^2 at rank `lane`, then suffix sums over rank:
+    // the dropped energy when the first rho coefficients are kept.
+    uint64_t x = e * (uint64_t)(kDp[pos >> 3] * kDp[pos & 7]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t o = __shfl_down(x, off, 64);
+      if (lane + off < 64) x += o;
+    }
+    if (lane >= P.r && lane < P.r + P.r_count && x != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(P.sse + (lane - P.r)),
+                (unsigned long long)(576ull * x));
+  }
+  }
+}
+
+// Register budget: the float64 reconstruction of the quantisation path keeps a
+// whole 8x8 float64 block live and is given a full wave-per-SIMD budget; every
+// other variant runs two waves per SIMD.
+template <int SEL, bool RECON, int EV>
+struct WideRegs {
+  static constexpr bool value = (SEL == SEL_Q) && (RECON || EV == EV_SPATIAL);
+};
+
+template <int SEL, int CO, bool RECON, int EV>
+__device__ __forceinline__ void plane_kernel_body(const Plane& P, const QuantConsts& qc,
+                                                  const ScaleConsts& sc) {
+  extern __shared__ uint32_t lds[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int chunk = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int t0 = chunk * 128;
+  if (t0 >= P.nblocks) return;
+  plane_chunk<SEL, CO, RECON, EV>(P, qc, sc, t0, lane, lds + wave * (64 * 65));
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+__global__ __launch_bounds__(256, 2) void k_plane(Plane P, QuantConsts qc, ScaleConsts sc) {
+  plane_kernel_body<SEL, CO, RECON, EV>(P, qc, sc);
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+__global__ __launch_bounds__(256, 1) void k_plane_w(Plane P, QuantConsts qc, ScaleConsts sc) {
+  plane_kernel_body<SEL, CO, RECON, EV>(P, qc, sc);
+}
+
+// Persistent batch kernel: workgroups stride over a device work list; each wave
+// takes items wave_id, wave_id + n_waves, ...  Every wave runs to the end of the
+// list, so the grid drains without any device-side queue.
+template <int SEL, int CO, bool RECON, int EV>
+__device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ planes,
+                                                  const QuantConsts* __restrict__ tables,
+                                                  const ScaleConsts* __restrict__ scp,
+                                                  const WorkItem* __restrict__ items,
+                                                  int n_items) {
+  extern __shared__ uint32_t lds[];
+  const int wpg = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n_waves = gridDim.x * wpg;
+  for (int it = blockIdx.x * wpg + wave; it < n_items; it += n_waves) {
+    const WorkItem w = items[it];
+    const Plane& P = planes[w.plane];
+    plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, w.t0, lane, lds + wave * (64 * 65));
+  }
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+__global__ __launch_bounds__(256, 2) void k_batch(const Plane* __restrict__ planes,
+                                                  const QuantConsts* __restrict__ tables,
+                                                  const ScaleConsts* __restrict__ scp,
+                                                  const WorkItem* __restrict__ items, int n_items) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, scp, items, n_items);
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+__global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ planes,
+                                                    const QuantConsts* __restrict__ tables,
+                                                    const ScaleConsts* __restrict__ scp,
+                                                    const WorkItem* __restrict__ items,
+                                                    int n_items) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, scp, items, n_items);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse from coefficients: one block per lane.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, Plane P,
+                                                 QuantConsts qc, ScaleConsts sc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.nblocks) return;
+  const int by = t / P.nbx, bx = t - by * P.nbx;
+  const int x0 = bx * 8, y0 = by * 8;
+  if constexpr (KIND == INV_INT_I32 || KIND == INV_INT_I16) {
+    const uint64_t keep = P.keep;
+    int w[8][8];
+    if constexpr (KIND == INV_INT_I32) {
+      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)t * 16;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int4 u = p[2 * k], s = p[2 * k + 1];
+        w[k][0] = u.x; w[k][1] = u.y; w[k][2] = u.z; w[k][3] = u.w;
+        w[k][4] = s.x; w[k][5] = s.y; w[k][6] = s.z; w[k][7] = s.w;
+      }
+    } else {
+      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)t * 8;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint4 u = p[k];
+        const uint32_t d[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          w[k][2 * m] = (int)(short)(d[m] & 0xffffu);
+          w[k][2 * m + 1] = (int)(short)(d[m] >> 16);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        w[k][l] = ((keep >> (k * 8 + l)) & 1) ? w[k][l] * (kDp[k] * kDp[l]) : 0;
+    pass2d<int, false>(w);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        px[j] = (float)__builtin_fma((double)w[i][j], 1.0 / 576.0, (double)P.shift);
+      store_row(P, x0, y0 + i, px);
+    }
+  } else {
+    double w[8][8];
+    if constexpr (KIND == INV_F32) {
+      const uint64_t keep = P.keep;
+      const float4* p = reinterpret_cast<const float4*>(coef) + (int64_t)t * 16;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float4 u = p[2 * k], s = p[2 * k + 1];
+        const float z[8] = {u.x, u.y, u.z, u.w, s.x, s.y, s.z, s.w};
+#pragma unroll
+        for (int l = 0; l < 8; ++l)
+          w[k][l] = ((keep >> (k * 8 + l)) & 1) ? (double)z[l] * sc.ss[k * 8 + l] : 0.0;
+      }
+    } else if constexpr (KIND == INV_Q_I32) {
+      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)t * 16;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int4 u = p[2 * k], s = p[2 * k + 1];
+        const int q[8] = {u.x, u.y, u.z, u.w, s.x, s.y, s.z, s.w};
+#pragma unroll
+        for (int l = 0; l < 8; ++l) w[k][l] = (double)q[l] * qc.dq[k * 8 + l];
+      }
+    } else {
+      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)t * 8;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint4 u = p[k];
+        const uint32_t d[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          w[k][2 * m] = (double)(int)(short)(d[m] & 0xffffu) * qc.dq[k * 8 + 2 * m];
+          w[k][2 * m + 1] = (double)(int)(short)(d[m] >> 16) * qc.dq[k * 8 + 2 * m + 1];
+        }
+      }
+    }
+    pass2d<double, false>(w);
+    const double sh = (double)P.shift;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) px[j] = (float)(w[i][j] + sh);
+      store_row(P, x0, y0 + i, px);
+    }
+  }
+}
+
+__global__ void k_zero_u64(uint64_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <int SEL, int CO, bool RECON, int EV>
+static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, const ScaleConsts& sc,
+                                 int wpg, hipStream_t s) {
+  const int chunks = (P.nblocks + 127) / 128;
+  const int grid = (chunks + wpg - 1) / wpg;
+  const size_t lds = (EV == EV_SWEEP) ? (size_t)wpg * 64 * 65 * 4 : 0;
+  if constexpr (WideRegs<SEL, RECON, EV>::value)
+    hipLaunchKernelGGL((k_plane_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
+  else
+    hipLaunchKernelGGL((k_plane<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
+  return hipGetLastError();
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
+                                 const ScaleConsts* scp, const WorkItem* items, int n_items,
+                                 int grid, int wpg, hipStream_t s) {
+  const size_t lds = (EV == EV_SWEEP) ? (size_t)wpg * 64 * 65 * 4 : 0;
+  if constexpr (WideRegs<SEL, RECON, EV>::value)
+    hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
+                       tables, scp, items, n_items);
+  else
+    hipLaunchKernelGGL((k_batch<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
+                       tables, scp, items, n_items);
+  return hipGetLastError();
+}
+
+// Dispatch table over the supported (selection, output, reconstruction, eval)
+// combinations.
+#define RDCT_DISPATCH(FN, ...)                                                           \
+  switch (sel * 1000 + co * 100 + (recon ? 10 : 0) + ev) {                               \
+    case SEL_ZZ * 1000 + CO_I32 * 100 + 0 + EV_NONE: return FN<SEL_ZZ, CO_I32, false, EV_NONE>(__VA_ARGS__); \
+    case SEL_ZZ * 1000 + CO_I16 * 100 + 0 + EV_NONE: return FN<SEL_ZZ, CO_I16, false, EV_NONE>(__VA_ARGS__); \
+    case SEL_ZZ * 1000 + CO_F32 * 100 + 0 + EV_NONE: return FN<SEL_ZZ, CO_F32, false, EV_NONE>(__VA_ARGS__); \
+    case SEL_Q * 1000 + CO_I32 * 100 + 0 + EV_NONE: return FN<SEL_Q, CO_I32, false, EV_NONE>(__VA_ARGS__);   \
+    case SEL_Q * 1000 + CO_I16 * 100 + 0 + EV_NONE: return FN<SEL_Q, CO_I16, false, EV_NONE>(__VA_ARGS__);   \
+    RDCT_EVAL_CASES(FN, EV_SPATIAL, __VA_ARGS__)                                         \
+    RDCT_EVAL_CASES(FN, EV_SWEEP, __VA_ARGS__)                                           \
+    RDCT_QEVAL_CASES(FN, __VA_ARGS__)                                                    \
+    default: return hipErrorInvalidValue;                                                \
+  }
+#define RDCT_EVAL_CASE(FN, CO, R, EV, ...) \
+  case SEL_ZZ * 1000 + CO * 100 + (R ? 10 : 0) + EV: return FN<SEL_ZZ, CO, R, EV>(__VA_ARGS__);
+#define RDCT_EVAL_CASES(FN, EV, ...)                                              \
+  RDCT_EVAL_CASE(FN, CO_NONE, false, EV, __VA_ARGS__) RDCT_EVAL_CASE(FN, CO_NONE, true, EV, __VA_ARGS__) \
+  RDCT_EVAL_CASE(FN, CO_I32, false, EV, __VA_ARGS__) RDCT_EVAL_CASE(FN, CO_I32, true, EV, __VA_ARGS__)   \
+  RDCT_EVAL_CASE(FN, CO_I16, false, EV, __VA_ARGS__) RDCT_EVAL_CASE(FN, CO_I16, true, EV, __VA_ARGS__)   \
+  RDCT_EVAL_CASE(FN, CO_F32, false, EV, __VA_ARGS__) RDCT_EVAL_CASE(FN, CO_F32, true, EV, __VA_ARGS__)
+#define RDCT_QEVAL_CASE(FN, CO, R, ...) \
+  case SEL_Q * 1000 + CO * 100 + (R ? 10 : 0) + EV_SPATIAL: return FN<SEL_Q, CO, R, EV_SPATIAL>(__VA_ARGS__);
+#define RDCT_QEVAL_CASE2(FN, CO, R, EV, ...) \
+  case SEL_Q * 1000 + CO * 100 + (R ? 10 : 0) + EV: return FN<SEL_Q, CO, R, EV>(__VA_ARGS__);
+#define RDCT_QEVAL_CASES(FN, ...)                                                      \
+  RDCT_QEVAL_CASE(FN, CO_NONE, false, __VA_ARGS__) RDCT_QEVAL_CASE(FN, CO_NONE, true, __VA_ARGS__) \
+  RDCT_QEVAL_CASE(FN, CO_I32, false, __VA_ARGS__) RDCT_QEVAL_CASE(FN, CO_I32, true, __VA_ARGS__)   \
+  RDCT_QEVAL_CASE(FN, CO_I16, false, __VA_ARGS__) RDCT_QEVAL_CASE(FN, CO_I16, true, __VA_ARGS__)   \
+  RDCT_QEVAL_CASE2(FN, CO_NONE, false, EV_COEF, __VA_ARGS__)                                        \
+  RDCT_QEVAL_CASE2(FN, CO_NONE, true, EV_COEF, __VA_ARGS__)                                         \
+  RDCT_QEVAL_CASE2(FN, CO_I32, false, EV_COEF, __VA_ARGS__)                                         \
+  RDCT_QEVAL_CASE2(FN, CO_I32, true, EV_COEF, __VA_ARGS__)                                          \
+  RDCT_QEVAL_CASE2(FN, CO_I16, false, EV_COEF, __VA_ARGS__)                                         \
+  RDCT_QEVAL_CASE2(FN, CO_I16, true, EV_COEF, __VA_ARGS__)
+
+hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
+                        const QuantConsts& qc, const ScaleConsts& sc, int wpg, hipStream_t s) {
+  if (P.nblocks <= 0) return hipSuccess;
+  RDCT_DISPATCH(launch_plane_t, P, qc, sc, wpg, s)
+}
+
+hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
+                        const QuantConsts* tables, const ScaleConsts* scp, const WorkItem* items,
+                        int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  RDCT_DISPATCH(launch_batch_t, planes, tables, scp, items, n_items, grid, wpg, s)
+}
+
+hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height, int32_t r,
+                          int32_t shift, float* dst, int64_t dpitch, const QuantConsts& qc,
+                          const ScaleConsts& sc, hipStream_t s) {
+  Plane P{};
+  P.width = width;
+  P.height = height;
+  P.nbx = (width + 7) / 8;
+  P.nby = (height + 7) / 8;
+  P.nblocks = P.nbx * P.nby;
+  P.recon = dst;
+  P.rpitch = dpitch;
+  P.r = r;
+  P.keep = keep_bits(r);
+  P.shift = shift;
+  if (P.nblocks <= 0) return hipSuccess;
+  const dim3 grid((P.nblocks + 255) / 256), block(256);
+  switch (kind) {
+    case INV_INT_I32: hipLaunchKernelGGL(k_inverse<INV_INT_I32>, grid, block, 0, s, coef, P, qc, sc); break;
+    case INV_INT_I16: hipLaunchKernelGGL(k_inverse<INV_INT_I16>, grid, block, 0, s, coef, P, qc, sc); break;
+    case INV_F32: hipLaunchKernelGGL(k_inverse<INV_F32>, grid, block, 0, s, coef, P, qc, sc); break;
+    case INV_Q_I32: hipLaunchKernelGGL(k_inverse<INV_Q_I32>, grid, block, 0, s, coef, P, qc, sc); break;
+    case INV_Q_I16: hipLaunchKernelGGL(k_inverse<INV_Q_I16>, grid, block, 0, s, coef, P, qc, sc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace rdct

@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/*.h declares, and rejects bad arguments before launching anything."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+import torch
+
+from conftest import ROOT
+
+R = pytest.importorskip("paper_1402_6034_amd.rdct")
+
+
+def _declared_symbols():
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        for m in re.finditer(r"\b(rdct_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_core_path():
+    names = _declared_symbols()
+    for n in ("rdct_forward", "rdct_inverse", "rdct_compress_eval", "rdct_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = R.lib()
+    missing = [n for n in _declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_units():
+    assert R.lib().rdct_status_string(R.ERR_INVALID_ARG).decode() == "invalid argument"
+    assert R.rdct_sse_unit(R.SEL_ZIGZAG) == 1.0 / 576 ** 2
+    assert R.rdct_sse_unit(R.SEL_QUANT) == 2.0 ** -20
+    assert R.rdct_psnr(0, R.SEL_ZIGZAG, 8, 8) == float("inf")
+    # sse = 576^2 * 64 * 255^2 over an 8x8 plane: MSE = 255^2 -> 0 dB.
+    assert abs(R.rdct_psnr(576 ** 2 * 64 * 255 ** 2, R.SEL_ZIGZAG, 8, 8)) < 1e-12
+    assert R.rdct_num_blocks(9, 17) == 2 * 3
+    assert R.rdct_num_blocks(0, 5) == 0
+
+
+# Fake, never-dereferenced addresses: every case below must be rejected during
+# validation.  Skipped when a GPU is present so that a validation bug could never
+# turn into a launch on a fake pointer.
+needs_no_gpu = pytest.mark.skipif(torch.cuda.is_available(), reason="host-only validation checks")
+FAKE_SRC, FAKE_DST, FAKE_SSE = 1 << 20, 1 << 21, 1 << 22
+
+
+def _fwd(src, w, h, pitch, sel, coef, ctype):
+    return R.lib().rdct_forward(src, w, h, pitch, ctypes.byref(sel), coef, ctype, None)
+
+
+@needs_no_gpu
+@pytest.mark.parametrize("case", [
+    dict(src=None), dict(w=0), dict(h=-1), dict(pitch=7), dict(coef=None),
+    dict(coef=FAKE_DST + 4), dict(ctype=9), dict(sel=R.select(R.SEL_ZIGZAG, r=0)),
+    dict(sel=R.select(R.SEL_ZIGZAG, r=65)), dict(sel=R.select(R.SEL_QUANT, quality=0)),
+    dict(sel=R.select(R.SEL_QUANT, quality=101)), dict(sel=R.select(R.SEL_QUANT, qtable=[0] * 64)),
+    dict(sel=R.select(R.SEL_QUANT, quality=50), ctype=R.COEF_F32),
+    dict(sel=R.select(R.SEL_NONE, level_shift=256)), dict(sel=R.select(7)),
+])
+def test_forward_rejects(case):
+    a = dict(src=FAKE_SRC, w=16, h=16, pitch=16, sel=R.select(R.SEL_NONE), coef=FAKE_DST,
+             ctype=R.COEF_I32)
+    a.update(case)
+    assert _fwd(a["src"], a["w"], a["h"], a["pitch"], a["sel"], a["coef"], a["ctype"]) == R.ERR_INVALID_ARG
+
+
+@needs_no_gpu
+def test_forward_rejects_huge_plane_as_unsupported():
+    assert _fwd(FAKE_SRC, 70000, 70000, 70000, R.select(R.SEL_NONE), FAKE_DST,
+                R.COEF_I32) == R.ERR_UNSUPPORTED
+
+
+def _eval(sel, r_count=1, w=64, h=64, sse=FAKE_SSE, coef=None, ctype=R.COEF_I32, recon=None,
+          rpitch=0):
+    return R.lib().rdct_compress_eval(FAKE_SRC, w, h, w, ctypes.byref(sel), r_count, coef, ctype,
+                                      recon, rpitch, sse, None)
+
+
+@needs_no_gpu
+def test_compress_eval_rejects():
+    z = R.select(R.SEL_ZIGZAG, r=20)
+    q = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+    assert _eval(z, sse=None) == R.ERR_INVALID_ARG
+    assert _eval(z, r_count=0) == R.ERR_INVALID_ARG
+    assert _eval(z, r_count=46) == R.ERR_INVALID_ARG          # r up to 65
+    assert _eval(q, r_count=2) == R.ERR_INVALID_ARG
+    assert _eval(R.select(R.SEL_NONE), r_count=2) == R.ERR_INVALID_ARG
+    assert _eval(z, recon=FAKE_DST, rpitch=10) == R.ERR_INVALID_ARG
+    assert _eval(q, coef=FAKE_DST, ctype=R.COEF_F32) == R.ERR_INVALID_ARG
+    assert _eval(z, r_count=2, w=60) == R.ERR_UNSUPPORTED     # sweep needs whole blocks
+    assert _eval(z, w=24000, h=20000) == R.ERR_UNSUPPORTED    # 7.5 M blocks: beyond the SSE range
+
+
+@needs_no_gpu
+def test_inverse_rejects():
+    L = R.lib()
+    sel = R.select(R.SEL_ZIGZAG, r=10)
+    assert L.rdct_inverse(None, R.COEF_I32, 8, 8, ctypes.byref(sel), FAKE_DST, 8, None) == R.ERR_INVALID_ARG
+    assert L.rdct_inverse(FAKE_SRC, R.COEF_I32, 8, 8, ctypes.byref(sel), FAKE_DST, 4, None) == R.ERR_INVALID_ARG
+    qs = R.select(R.SEL_QUANT, quality=50)
+    assert L.rdct_inverse(FAKE_SRC, R.COEF_F32, 8, 8, ctypes.byref(qs), FAKE_DST, 8, None) == R.ERR_INVALID_ARG
