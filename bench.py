@@ -162,17 +162,117 @@ class PlainSweep:
                 "sample": f"{n} of the 256 planes, r = 1..45 each (inverse per r, exact SSE)"}
 
 
-WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep}
+class RaggedBatch:
+    """1000 planes, width and height independently log-uniform in [64, 4096]
+    (multiples of 8), quality uniform in 10..90: forward + S-scaled quantisation
+    + inverse + per-plane PSNR in one persistent launch over a device-side block
+    work list (hipGraph replay, autotuned geometry); int16 coefficients and the
+    float32 reconstruction are written to HBM."""
+    name = "ragged-1000-logU64-4096-q10-90"
+
+    def __init__(self, n=1000, planes_cache=None, autotune=True):
+        import numpy as np
+        import torch
+        from paper_1402_6034_amd import rdct as R, synth
+        self.R = R
+        self.items = synth.ragged_batch(0, n)
+        if planes_cache and os.path.exists(planes_cache):
+            log(f"[bench] loading {n} ragged planes from {planes_cache}")
+            flat = np.load(planes_cache, mmap_mode="r")
+            self.imgs, off = [], 0
+            for it in self.items:
+                k = it.height * it.width
+                self.imgs.append(torch.from_numpy(np.array(flat[off:off + k]).reshape(it.height, it.width)).cuda())
+                off += k
+        else:
+            log(f"[bench] rendering {n} ragged planes")
+            self.imgs = [synth.render(it.seed, it.height, it.width, device="cuda") for it in self.items]
+            if planes_cache:
+                np.save(planes_cache, np.concatenate([im.cpu().numpy().reshape(-1) for im in self.imgs]))
+        torch.cuda.synchronize()
+        self.sels = [R.select(R.SEL_QUANT, quality=it.quality, level_shift=128) for it in self.items]
+        self.plan = R.BatchPlan(self.imgs, self.sels, R.COEF_I16, recon=True)
+        self.nb = self.plan.n_blocks
+        log(f"[bench] plan: {self.nb} blocks in {self.plan.n_items} work items")
+        if autotune:
+            t = self.plan.autotune(reps=3)
+            log(f"[bench] tuned geometry: {t.waves_per_wg} waves/WG x {t.wgs_per_cu} WGs/CU")
+        self.px = sum(it.height * it.width for it in self.items)
+        self.psnr = None
+
+    def launch(self, i=0):
+        self.plan.run()
+
+    kernel_launch = launch
+
+    def step(self):
+        import numpy as np
+        self.plan.run()
+        s = self.plan.sse.cpu().numpy().astype(np.float64) * 2.0 ** -20
+        npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
+        with np.errstate(divide="ignore"):
+            self.psnr = 10.0 * np.log10(255.0 ** 2 / (s / npx))
+
+    blocks_per_step = property(lambda self: self.nb)
+    bytes_per_block = 64 + 128 + 256
+
+    def config(self):
+        t = self.plan.tuning
+        return {"workload": self.name, "planes": len(self.items), "blocks": self.nb,
+                "pixels": self.px, "coef": "int16", "recon": "float32", "level_shift": 128,
+                "waves_per_wg": t.waves_per_wg, "wgs_per_cu": t.wgs_per_cu,
+                "graph": bool(t.use_graph)}
+
+    def plain(self, steps=2):
+        """Same planes through the plain path: one rdct_compress_eval launch per plane."""
+        import torch
+        R = self.R
+        outs = [(torch.empty((R.rdct_num_blocks(im.shape[1], im.shape[0]), 64), dtype=torch.int16,
+                             device="cuda"), torch.empty(im.shape, dtype=torch.float32, device="cuda"))
+                for im in self.imgs]
+        sse = torch.empty((len(self.imgs), 1), dtype=torch.int64, device="cuda")
+
+        def once():
+            for k, (im, sel) in enumerate(zip(self.imgs, self.sels)):
+                R.compress_eval(im, sel, 1, R.COEF_I16, True, sse=sse[k], coef=outs[k][0],
+                                recon_out=outs[k][1])
+            sse.cpu()
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            once()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        same = bool(torch.equal(sse[:, 0], self.plan.sse))
+        return {"value": round(self.nb / (ms * 1e-3) / 1e6, 3), "unit": "Mblocks/s",
+                "ms_per_step": round(ms, 4), "launches_per_step": 2 * len(self.imgs),
+                "identical_sse": same}
+
+    def cpu_baseline(self, budget_s):
+        import oracle as O
+        t0 = time.perf_counter()
+        blocks = n = 0
+        order = sorted(range(len(self.items)), key=lambda k: self.items[k].height * self.items[k].width)
+        while time.perf_counter() - t0 < budget_s and n < len(order):
+            it = self.items[order[n]]
+            O.quant_eval(self.imgs[order[n]].cpu().numpy(), O.quant_table(it.quality))
+            blocks += (it.height // 8) * (it.width // 8)
+            n += 1
+        dt = time.perf_counter() - t0
+        return {"value": blocks / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
+                "kind": "oracle",
+                "sample": f"the {n} smallest of the 1000 planes ({blocks} blocks), forward + "
+                          "exact quantisation + float64 inverse + SSE"}
+
+
+WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch}
 
 
 def _oracle_threads():
-    try:
-        import numpy as np  # noqa: F401
-        from threadpoolctl import threadpool_info
-        n = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        return int(n)
-    except Exception:
-        return 1
+    """The oracle runs in one process with its BLAS pool limited to one thread
+    (see main), so it uses one core."""
+    return 1
 
 
 def main():
@@ -180,9 +280,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="frame", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ragged", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="ragged: use the tuning cache (or defaults) instead of tuning first")
+    ap.add_argument("--planes-cache", default=None,
+                    help="ragged: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB mebibytes device-to-device 3 times "
+                         "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one MI355X only; multi-GPU runs are not provided "
@@ -193,7 +301,10 @@ def main():
     from paper_1402_6034_amd import rdct as R
     R.lib()
     torch.cuda.init()
-    wl = WORKLOADS[args.workload]()
+    if args.workload == "ragged":
+        wl = RaggedBatch(planes_cache=args.planes_cache, autotune=not args.no_autotune)
+    else:
+        wl = WORKLOADS[args.workload]()
 
     for _ in range(args.warmup):
         wl.step()
@@ -222,15 +333,32 @@ def main():
     cpu = None
     if args.cpu_budget > 0:
         log("[bench] timing the CPU oracle on a sample")
-        cpu = wl.cpu_baseline(args.cpu_budget)
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            cpu = wl.cpu_baseline(args.cpu_budget)
 
     value = wl.blocks_per_step / (ms * 1e-3) / 1e6
+    plain = None
+    if hasattr(wl, "plain") and not args.no_plain:
+        log("[bench] timing the plain one-launch-per-plane path")
+        plain = wl.plain()
+
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mblocks/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int16+f64", "data": "synthetic", "config": wl.config(),
            "roofline": roofline, "cpu_baseline": cpu}
+    if plain is not None:
+        out["plain"] = plain
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {n} bytes x3 done")
 
 
 if __name__ == "__main__":

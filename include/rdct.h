@@ -148,6 +148,70 @@ double rdct_psnr(uint64_t sse, int32_t mode, int32_t width, int32_t height);
 /* Number of 8x8 blocks of a plane: ceil(h/8) * ceil(w/8). */
 int64_t rdct_num_blocks(int32_t width, int32_t height);
 
+/* ------------------------------------------------------------------------- */
+/* Batched planes: one persistent launch over a device-side block work list   */
+/* ------------------------------------------------------------------------- */
+
+/* One plane of a batch.  Pointers are DEVICE pointers that must stay valid
+   while the plan exists (the plan records them). */
+typedef struct {
+  const uint8_t* src;      /* plane, height rows of src_pitch bytes              */
+  int32_t width, height;
+  int64_t src_pitch;
+  rdct_select_t sel;       /* per-plane r / quality / table / level shift; the
+                              mode (ZIGZAG or QUANT; NONE = ZIGZAG with r = 64)
+                              must be the same for every plane of a plan          */
+  void* coef_out;          /* block-major coefficients (nullable; null for all
+                              planes or for none)                                 */
+  float* recon_out;        /* reconstruction (nullable; null for all or none)     */
+  int64_t recon_pitch;     /* floats per reconstruction row                       */
+} rdct_plane_desc_t;
+
+/* Launch geometry of the persistent kernel. */
+typedef struct {
+  int32_t waves_per_wg;    /* 1, 2 or 4; 0 = from the tuning cache or default      */
+  int32_t wgs_per_cu;      /* resident workgroups per compute unit, 1..16; 0 = same */
+  int32_t use_graph;       /* 1: runs replay a captured hipGraph; 0: plain launches */
+  int32_t reserved;
+} rdct_tuning_t;
+
+typedef struct rdct_batch_plan rdct_batch_plan_t;
+
+/*
+ * Build a plan over n planes (Section 3's per-block procedure applied to every
+ * block of every plane): a device work list of 128-block items, the per-plane
+ * descriptors and quantisation tables are uploaded once.  Each run computes,
+ * for every plane, what rdct_compress_eval computes with r_count = 1 (same
+ * kernels, identical per-block results): coefficients, reconstruction and
+ * sse_out[i] (units of rdct_sse_unit(mode)), overwritten.
+ * Allocates device memory (the plan's tables) -- not a hot call.
+ * tuning: NULL = tuning cache or defaults.
+ * Errors: INVALID_ARG (any plane invalid, mixed modes or output nullness),
+ * UNSUPPORTED, NO_MEMORY, HIP.
+ */
+rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
+                                     rdct_coef_t coef_type, uint64_t* sse_out,
+                                     const rdct_tuning_t* tuning, rdct_batch_plan_t** out);
+
+/* Run the plan on `stream` (asynchronous; no allocation).  With use_graph the
+   first run captures the launch sequence into a hipGraph; later runs replay it. */
+rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
+
+/* Blocks and work items of a plan, and the geometry it runs with (any pointer
+   may be NULL). */
+rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
+                                   int32_t* n_items, rdct_tuning_t* used);
+
+/* Time every candidate geometry on this plan (reps launches each, median of
+   HIP-event durations, synchronous), adopt the fastest, store it in the tuning
+   cache (file named by RDCT_TUNING_CACHE, default ~/.cache/rdct_tuning.json,
+   keyed by architecture, path variant and size class) and return it in *best. */
+rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* stream,
+                                  rdct_tuning_t* best);
+
+/* Release the plan's device memory and graph (synchronises its internal stream). */
+void rdct_batch_plan_destroy(rdct_batch_plan_t* plan);
+
 const char* rdct_status_string(rdct_status_t status);
 
 /* Library version string and the GPU architecture it was built for. */

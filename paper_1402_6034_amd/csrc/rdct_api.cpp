@@ -1,5 +1,6 @@
 // C-ABI front end of librdct: argument validation, constant tables, dispatch.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -44,7 +45,13 @@ uint64_t keep_bits(int r) {
   return m;
 }
 
-static std::atomic<int> g_waves_per_wg{4};
+static int initial_waves_per_wg() {
+  // RDCT_WAVES_PER_WG overrides the default workgroup shape (1, 2 or 4 waves).
+  const char* e = getenv("RDCT_WAVES_PER_WG");
+  const int v = e ? atoi(e) : 1;
+  return (v == 1 || v == 2 || v == 4) ? v : 1;
+}
+static std::atomic<int> g_waves_per_wg{initial_waves_per_wg()};  // measured best: 1
 
 int device_cu_count() {
   int dev = 0, n = 0;
@@ -55,9 +62,8 @@ int device_cu_count() {
 }
 
 int default_waves_per_wg() { return g_waves_per_wg.load(); }
-void set_default_waves_per_wg(int w) { g_waves_per_wg.store(w); }
 
-static const ScaleConsts& scale_consts() {
+const ScaleConsts& scale_consts() {
   static const ScaleConsts sc = [] {
     ScaleConsts s;
     fill_scale_consts(&s);
@@ -66,15 +72,7 @@ static const ScaleConsts& scale_consts() {
   return sc;
 }
 
-// Validated selection: effective mode, r and the quantisation constants.
-struct SelInfo {
-  int sel;      // SEL_ZZ or SEL_Q
-  int r;        // ZZ: 1..64 (NONE -> 64)
-  int shift;
-  QuantConsts qc;
-};
-
-static rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out) {
+rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out) {
   if (!s) return RDCT_ERR_INVALID_ARG;
   if (s->level_shift < 0 || s->level_shift > 255) return RDCT_ERR_INVALID_ARG;
   out->shift = s->level_shift;
@@ -101,6 +99,7 @@ static rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out) {
         ijg_table(s->quality, q);
       }
       fill_quant_consts(q, &out->qc);
+      memcpy(out->q, q, sizeof(q));
       out->sel = SEL_Q;
       out->r = 64;
       return RDCT_OK;
@@ -119,12 +118,10 @@ static int coef_kind(rdct_coef_t t) {
   }
 }
 
-static bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
-static constexpr int64_t kMaxBlocks = 1ll << 26;      // transform calls
-static constexpr int64_t kMaxEvalBlocks = 6000000;     // uint64 SSE sums cannot wrap
 
-static rdct_status_t check_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch,
+rdct_status_t check_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch,
                                  int64_t max_blocks) {
   if (!src || w <= 0 || h <= 0 || pitch < w) return RDCT_ERR_INVALID_ARG;
   const int64_t nb = (int64_t)((w + 7) / 8) * ((h + 7) / 8);

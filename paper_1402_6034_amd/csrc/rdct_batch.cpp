@@ -1,0 +1,316 @@
+// Batch planner: many planes of uneven sizes in one persistent launch.
+//
+// A plan uploads, once, a device work list of 128-block items (plane, first
+// block), the per-plane descriptors and the distinct quantisation tables.  A
+// run zeroes the per-plane error sums with a small kernel and launches the
+// persistent kernel, whose waves stride over the work list; both launches can
+// be captured into a hipGraph and replayed.  Per-block arithmetic is the same
+// device code as the single-plane calls, so every plane's outputs are identical
+// whether it is processed alone or inside a batch.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rdct_internal.h"
+#include "rdct_tables.h"
+#include "rdct_tune.h"
+
+using namespace rdct;
+
+struct rdct_batch_plan {
+  int sel = SEL_ZZ, co = CO_NONE, ev = EV_SPATIAL;
+  bool recon = false;
+  int32_t n_planes = 0, n_items = 0;
+  int64_t n_blocks = 0;
+  uint64_t* sse = nullptr;
+  Plane* d_planes = nullptr;
+  QuantConsts* d_tables = nullptr;
+  ScaleConsts* d_sc = nullptr;
+  WorkItem* d_items = nullptr;
+  rdct_tuning_t tuning{};
+  int device = 0;
+  int n_cu = 256;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graph_ready = false;
+  std::string key;
+};
+
+namespace {
+
+void free_plan(rdct_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) {
+    hipStreamSynchronize(p->cap_stream);
+    hipStreamDestroy(p->cap_stream);
+  }
+  if (p->d_planes) hipFree(p->d_planes);
+  if (p->d_tables) hipFree(p->d_tables);
+  if (p->d_sc) hipFree(p->d_sc);
+  if (p->d_items) hipFree(p->d_items);
+  delete p;
+}
+
+int grid_of(const rdct_batch_plan* p, const rdct_tuning_t& t) {
+  const int wpg = t.waves_per_wg;
+  const int max_grid = (p->n_items + wpg - 1) / wpg;
+  return std::max(1, std::min(p->n_cu * t.wgs_per_cu, max_grid));
+}
+
+hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t s) {
+  hipError_t e = launch_zero_u64(p->sse, p->n_planes, s);
+  if (e != hipSuccess) return e;
+  return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables, p->d_sc,
+                      p->d_items, p->n_items, grid_of(p, t), t.waves_per_wg, s);
+}
+
+rdct_status_t capture(rdct_batch_plan* p) {
+  if (p->exec) {
+    hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+  }
+  if (p->graph) {
+    hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  p->graph_ready = false;
+  if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return RDCT_ERR_HIP;
+  const hipError_t le = launch_direct(p, p->tuning, p->cap_stream);
+  const hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
+  if (le != hipSuccess || ce != hipSuccess || !p->graph) return RDCT_ERR_HIP;
+  if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+    return RDCT_ERR_HIP;
+  p->graph_ready = true;
+  return RDCT_OK;
+}
+
+bool valid_tuning(const rdct_tuning_t& t) {
+  return (t.waves_per_wg == 1 || t.waves_per_wg == 2 || t.waves_per_wg == 4) &&
+         t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16;
+}
+
+std::string plan_key(const rdct_batch_plan* p) {
+  // Size class: log2 of the block count.
+  int cls = 0;
+  for (int64_t b = p->n_blocks; b > 1; b >>= 1) ++cls;
+  char buf[128];
+  snprintf(buf, sizeof(buf), "gfx950/batch/sel%d/co%d/recon%d/ev%d/log2blocks%d", p->sel, p->co,
+           p->recon ? 1 : 0, p->ev, cls);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
+                                     rdct_coef_t coef_type, uint64_t* sse_out,
+                                     const rdct_tuning_t* tuning, rdct_batch_plan_t** out) {
+  if (!out) return RDCT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!planes || n <= 0 || !sse_out || !aligned(sse_out, 8)) return RDCT_ERR_INVALID_ARG;
+  const bool want_coef = planes[0].coef_out != nullptr;
+  const bool want_recon = planes[0].recon_out != nullptr;
+  int co = CO_NONE;
+  if (want_coef) {
+    switch (coef_type) {
+      case RDCT_COEF_I32: co = CO_I32; break;
+      case RDCT_COEF_I16: co = CO_I16; break;
+      case RDCT_COEF_F32: co = CO_F32; break;
+      default: return RDCT_ERR_INVALID_ARG;
+    }
+  }
+  // Validate every plane and collect descriptors.
+  std::vector<Plane> hp(n);
+  std::vector<QuantConsts> tables;
+  std::map<std::vector<uint16_t>, int> table_index;
+  int sel_kind = -1;
+  bool all_full = true;
+  int64_t n_blocks = 0;
+  std::vector<WorkItem> items;
+  for (int i = 0; i < n; ++i) {
+    const rdct_plane_desc_t& d = planes[i];
+    rdct_status_t st = check_plane(d.src, d.width, d.height, d.src_pitch, kMaxEvalBlocks);
+    if (st != RDCT_OK) return st;
+    SelInfo si;
+    if ((st = check_sel(&d.sel, &si)) != RDCT_OK) return st;
+    if (sel_kind < 0) sel_kind = si.sel;
+    if (si.sel != sel_kind) return RDCT_ERR_INVALID_ARG;
+    if ((d.coef_out != nullptr) != want_coef || (d.recon_out != nullptr) != want_recon)
+      return RDCT_ERR_INVALID_ARG;
+    if (want_coef && !aligned(d.coef_out, 16)) return RDCT_ERR_INVALID_ARG;
+    if (want_recon && (d.recon_pitch < d.width || !aligned(d.recon_out, 4)))
+      return RDCT_ERR_INVALID_ARG;
+    if (si.sel == SEL_Q && co == CO_F32) return RDCT_ERR_INVALID_ARG;
+    Plane P = make_plane(d.src, d.width, d.height, d.src_pitch);
+    P.coef = d.coef_out;
+    P.recon = d.recon_out;
+    P.rpitch = d.recon_pitch;
+    P.sse = sse_out + i;
+    P.r = si.r;
+    P.keep = keep_bits(si.r);
+    P.r_count = 1;
+    P.shift = si.shift;
+    P.table = 0;
+    if (si.sel == SEL_Q) {
+      std::vector<uint16_t> key(si.q, si.q + 64);
+      auto it = table_index.find(key);
+      if (it == table_index.end()) {
+        it = table_index.emplace(key, (int)tables.size()).first;
+        tables.push_back(si.qc);
+      }
+      P.table = it->second;
+    }
+    if ((d.width % 8) != 0 || (d.height % 8) != 0) all_full = false;
+    hp[i] = P;
+    for (int t0 = 0; t0 < P.nblocks; t0 += 128) items.push_back(WorkItem{i, t0});
+    n_blocks += P.nblocks;
+  }
+  if (items.size() > (size_t)0x7fffffff) return RDCT_ERR_UNSUPPORTED;
+  if (tables.empty()) {
+    tables.emplace_back();
+    memset(&tables[0], 0, sizeof(QuantConsts));
+  }
+
+  rdct_batch_plan* p = new rdct_batch_plan();
+  p->sel = sel_kind;
+  p->co = co;
+  p->recon = want_recon;
+  p->ev = (sel_kind == SEL_Q && all_full) ? EV_COEF : EV_SPATIAL;
+  p->n_planes = n;
+  p->n_items = (int32_t)items.size();
+  p->n_blocks = n_blocks;
+  p->sse = sse_out;
+  p->n_cu = device_cu_count();
+  hipGetDevice(&p->device);
+  p->key = plan_key(p);
+
+  bool ok = hipMalloc(&p->d_planes, sizeof(Plane) * n) == hipSuccess &&
+            hipMalloc(&p->d_tables, sizeof(QuantConsts) * tables.size()) == hipSuccess &&
+            hipMalloc(&p->d_sc, sizeof(ScaleConsts)) == hipSuccess &&
+            hipMalloc(&p->d_items, sizeof(WorkItem) * items.size()) == hipSuccess;
+  if (!ok) {
+    free_plan(p);
+    return RDCT_ERR_NO_MEMORY;
+  }
+  ok = hipMemcpy(p->d_planes, hp.data(), sizeof(Plane) * n, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_tables, tables.data(), sizeof(QuantConsts) * tables.size(),
+                 hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_sc, &scale_consts(), sizeof(ScaleConsts), hipMemcpyHostToDevice) ==
+           hipSuccess &&
+       hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(),
+                 hipMemcpyHostToDevice) == hipSuccess &&
+       hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    free_plan(p);
+    return RDCT_ERR_HIP;
+  }
+
+  // Geometry: explicit > tuning cache > default.
+  rdct_tuning_t t{};
+  t.waves_per_wg = 1;
+  t.wgs_per_cu = 8;
+  t.use_graph = 1;
+  rdct_tuning_t cached;
+  if (tune_cache_lookup(p->key, &cached)) {
+    t.waves_per_wg = cached.waves_per_wg;
+    t.wgs_per_cu = cached.wgs_per_cu;
+  }
+  if (tuning) {
+    if (tuning->waves_per_wg) t.waves_per_wg = tuning->waves_per_wg;
+    if (tuning->wgs_per_cu) t.wgs_per_cu = tuning->wgs_per_cu;
+    t.use_graph = tuning->use_graph ? 1 : 0;
+  }
+  if (!valid_tuning(t)) {
+    free_plan(p);
+    return RDCT_ERR_INVALID_ARG;
+  }
+  p->tuning = t;
+  *out = p;
+  return RDCT_OK;
+}
+
+rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream) {
+  if (!plan) return RDCT_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (!plan->tuning.use_graph)
+    return launch_direct(plan, plan->tuning, s) == hipSuccess ? RDCT_OK : RDCT_ERR_HIP;
+  if (!plan->graph_ready) {
+    const rdct_status_t st = capture(plan);
+    if (st != RDCT_OK) return st;
+  }
+  return hipGraphLaunch(plan->exec, s) == hipSuccess ? RDCT_OK : RDCT_ERR_HIP;
+}
+
+rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
+                                   int32_t* n_items, rdct_tuning_t* used) {
+  if (!plan) return RDCT_ERR_INVALID_ARG;
+  if (n_blocks) *n_blocks = plan->n_blocks;
+  if (n_items) *n_items = plan->n_items;
+  if (used) *used = plan->tuning;
+  return RDCT_OK;
+}
+
+rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* stream,
+                                  rdct_tuning_t* best) {
+  if (!plan || reps < 1 || reps > 1000) return RDCT_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RDCT_ERR_HIP;
+  const int wpgs[] = {1, 2, 4};
+  const int per_cu_waves[] = {2, 4, 8, 12, 16};
+  float best_us = 1e30f;
+  rdct_tuning_t best_t = plan->tuning;
+  rdct_status_t st = RDCT_OK;
+  for (int wpg : wpgs) {
+    for (int waves : per_cu_waves) {
+      if (waves % wpg) continue;
+      rdct_tuning_t t = plan->tuning;
+      t.waves_per_wg = wpg;
+      t.wgs_per_cu = waves / wpg;
+      if (!valid_tuning(t)) continue;
+      // One untimed launch, then `reps` timed ones.
+      if (launch_direct(plan, t, s) != hipSuccess) { st = RDCT_ERR_HIP; break; }
+      std::vector<float> us;
+      for (int r = 0; r < reps && st == RDCT_OK; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess || launch_direct(plan, t, s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = RDCT_ERR_HIP;
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        us.push_back(ms * 1000.f);
+      }
+      if (st != RDCT_OK) break;
+      std::sort(us.begin(), us.end());
+      const float med = us[us.size() / 2];
+      if (med < best_us) {
+        best_us = med;
+        best_t = t;
+      }
+    }
+    if (st != RDCT_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != RDCT_OK) return st;
+  plan->tuning = best_t;
+  plan->graph_ready = false;  // re-captured on the next run
+  tune_cache_store(plan->key, best_t, best_us);
+  if (best) *best = best_t;
+  return RDCT_OK;
+}
+
+void rdct_batch_plan_destroy(rdct_batch_plan_t* plan) { free_plan(plan); }
+
+}  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/rdct.h"
+
 namespace rdct {
 
 // One plane as the kernels see it.
@@ -85,5 +87,25 @@ hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes
                         int32_t waves_per_wg, hipStream_t stream);
 
 int device_cu_count();
+int default_waves_per_wg();
+
+constexpr int64_t kMaxBlocks = 1ll << 26;   // transform calls
+constexpr int64_t kMaxEvalBlocks = 6000000;  // evaluation: the uint64 SSE sums cannot wrap
+
+// Validated selection: effective mode, r and the quantisation constants.
+struct SelInfo {
+  int sel;        // SEL_ZZ or SEL_Q
+  int r;          // ZZ: 1..64 (NONE -> 64)
+  int shift;
+  uint16_t q[64]; // SEL_Q: the quantisation table
+  QuantConsts qc;
+};
+rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out);
+rdct_status_t check_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch,
+                          int64_t max_blocks);
+Plane make_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch);
+bool aligned(const void* p, uintptr_t a);
+const ScaleConsts& scale_consts();
+
 
 }  // namespace rdct

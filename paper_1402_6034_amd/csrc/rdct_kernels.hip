@@ -24,6 +24,8 @@
 namespace rdct {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __constant__ ZigZag c_zz = make_zigzag();
 
@@ -105,7 +107,8 @@ __device__ __forceinline__ int quantize(int y, uint64_t qm) {
   } else {
     const double m = __longlong_as_double((long long)qm);
     const double yd = (double)y;
-    return (int)__builtin_fma(yd, m, __builtin_copysign(0.5, yd));
+    const double t = __builtin_fma(__builtin_fabs(yd), m, 0.5);
+    return (int)__builtin_copysign(t, yd);
   }
 }
 
@@ -129,7 +132,8 @@ __device__ __forceinline__ void load_block(const Plane& P, int t, bool valid, ui
     const uint8_t* base = P.src + (int64_t)y0 * P.pitch + x0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const uint2 r = *reinterpret_cast<const uint2*>(base + (int64_t)i * P.pitch);
+      const u32x2 r = __builtin_nontemporal_load(
+          reinterpret_cast<const u32x2*>(base + (int64_t)i * P.pitch));
       w[2 * i] = r.x;
       w[2 * i + 1] = r.y;
     }
@@ -234,6 +238,14 @@ __device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], ui
   }
 }
 
+// Store one reconstructed row of 8 pixels of a block that lies inside the plane,
+// on a plane whose rows are 16-byte aligned (checked on the host).
+__device__ __forceinline__ void store_row_full(const Plane& P, int x0, int y, const float (&px)[8]) {
+  float* row = P.recon + (int64_t)y * P.rpitch + x0;
+  reinterpret_cast<float4*>(row)[0] = make_float4(px[0], px[1], px[2], px[3]);
+  reinterpret_cast<float4*>(row)[1] = make_float4(px[4], px[5], px[6], px[7]);
+}
+
 // Store one reconstructed row of 8 pixels (clipped to the plane).
 __device__ __forceinline__ void store_row(const Plane& P, int x0, int y, const float (&px)[8]) {
   if (y >= P.height) return;
@@ -245,6 +257,48 @@ __device__ __forceinline__ void store_row(const Plane& P, int x0, int y, const f
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       if (x0 + j < P.width) row[j] = px[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient output through LDS.  A lane produces its block's 64 values in
+// natural order; written straight to HBM that is 16-byte pieces 128-256 bytes
+// apart across the wave, which splits every cache line between many requests.
+// Instead each lane writes its block into a per-wave LDS stage (block stride
+// padded by 16 bytes, so the eight lanes of one 128-byte LDS pass hit distinct
+// banks), and the wave then copies the stage out in order: every store
+// instruction covers 1 KB of contiguous output.
+// ---------------------------------------------------------------------------
+template <int CO>
+struct Stage {
+  static constexpr int bytes = (CO == CO_I16) ? 128 : 256;  // one block's coefficients
+  static constexpr int stride = bytes + 16;                   // padded LDS block stride
+  static constexpr int wave_bytes = (CO == CO_NONE) ? 0 : 64 * stride;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copy the stage of 64 consecutive blocks (first block t_first, `nvalid` of them
+// inside the plane) to the block-major output.
+template <int CO>
+__device__ __forceinline__ void flush_stage(const uint8_t* stage, void* coef, int64_t t_first,
+                                            int nvalid, int lane) {
+  constexpr int per_block = Stage<CO>::bytes / 16;   // 16-byte pieces per block
+  constexpr int pieces = 64 * per_block;
+  uint8_t* out = reinterpret_cast<uint8_t*>(coef) + t_first * Stage<CO>::bytes;
+  const int limit = nvalid * per_block;
+#pragma unroll
+  for (int m = 0; m < pieces / 64; ++m) {
+    const int c = lane + 64 * m;
+    const int b = c / per_block, o = c - b * per_block;
+    if (c < limit) {
+      const u32x4 val = *reinterpret_cast<const u32x4*>(stage + b * Stage<CO>::stride + o * 16);
+      __builtin_nontemporal_store(val, reinterpret_cast<u32x4*>(out + (int64_t)c * 16));
+    }
   }
 }
 
@@ -287,14 +341,16 @@ __device__ __forceinline__ uint64_t retention_inverse(const Plane& P, const s16x
   return (uint64_t)acc;  // exact: < 2^53 per block
 }
 
-// Quantise row K of block h of the pair, store it, and (RECON) dequantise it into
-// the float64 inverse input; (ERR) accumulate the coefficient-domain error.
-template <int K, int CO, bool RECON, bool ERR, int... L>
-__device__ __forceinline__ void quant_row(const s16x2 (&row)[8], int h, const QuantConsts& qc,
-                                          const ScaleConsts& sc, void* coef, int64_t t,
-                                          double (&w)[8][8], double& err,
+// Quantise row K of block h of the pair: store the row into the lane's stage,
+// (ERR) accumulate the coefficient-domain error, and write q back over half h of
+// the pair (the inverse reads it from there).
+template <int K, int CO, bool ERR, int... L>
+__device__ __forceinline__ void quant_row(s16x2 (&row)[8], int h, const QuantConsts& qc,
+                                          const ScaleConsts& sc, uint8_t* stage, double& err,
                                           std::integer_sequence<int, L...>) {
   int q[8];
+  // v_perm selectors that replace half h of a pair by the low half of q.
+  const uint32_t put = h ? 0x01000504u : 0x07060100u;
   auto one = [&](auto lc) {
     constexpr int l = decltype(lc)::value;
     constexpr int kl = K * 8 + l;
@@ -303,14 +359,14 @@ __device__ __forceinline__ void quant_row(const s16x2 (&row)[8], int h, const Qu
     q[l] = qq;
     if constexpr (ERR) {
       // z - q Q with z = s_k s_l Y: one rounding (FMA) per coefficient.
-      const double d = __builtin_fma((double)y, sc.ss[kl], -(double)(qq * qc.qi[kl]));
+      const double d = __builtin_fma((double)y, sc.ss[kl], -(double)__mul24(qq, qc.qi[kl]));
       err = __builtin_fma(d, d, err);
     }
-    if constexpr (RECON) w[K][l] = (double)qq * qc.dq[kl];
+    row[l] = as_pair(__builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, row[l]), (uint32_t)qq, put));
   };
   (one(std::integral_constant<int, L>{}), ...);
   if constexpr (CO == CO_I32) {
-    int4* out = reinterpret_cast<int4*>(reinterpret_cast<int32_t*>(coef) + t * 64 + K * 8);
+    int4* out = reinterpret_cast<int4*>(stage + K * 32);
     out[0] = make_int4(q[0], q[1], q[2], q[3]);
     out[1] = make_int4(q[4], q[5], q[6], q[7]);
   } else if constexpr (CO == CO_I16) {
@@ -318,56 +374,102 @@ __device__ __forceinline__ void quant_row(const s16x2 (&row)[8], int h, const Qu
 #pragma unroll
     for (int m = 0; m < 4; ++m)
       d[m] = ((uint32_t)q[2 * m] & 0xffffu) | ((uint32_t)q[2 * m + 1] << 16);
-    *reinterpret_cast<uint4*>(reinterpret_cast<int16_t*>(coef) + t * 64 + K * 8) =
-        make_uint4(d[0], d[1], d[2], d[3]);
+    *reinterpret_cast<uint4*>(stage + K * 16) = make_uint4(d[0], d[1], d[2], d[3]);
   }
 }
 
-template <int CO, bool RECON, bool ERR, int... K>
-__device__ __forceinline__ void quant_rows(const s16x2 (&v)[8][8], int h, const QuantConsts& qc,
-                                           const ScaleConsts& sc, void* coef, int64_t t,
-                                           double (&w)[8][8], double& err,
+template <int CO, bool ERR, int... K>
+__device__ __forceinline__ void quant_rows(s16x2 (&v)[8][8], int h, const QuantConsts& qc,
+                                           const ScaleConsts& sc, uint8_t* stage, double& err,
                                            std::integer_sequence<int, K...>) {
-  (quant_row<K, CO, RECON, ERR>(v[K], h, qc, sc, coef, t, w, err,
-                                std::make_integer_sequence<int, 8>{}), ...);
+  (quant_row<K, CO, ERR>(v[K], h, qc, sc, stage, err, std::make_integer_sequence<int, 8>{}), ...);
 }
 
-// Quantisation path for block h of the pair: q = round(z / Q) exactly, stored as
-// it is produced; W = q Q s_k s_l in float64, A' = C0^T W C0 + shift.
-// Returns round(2^20 * block SSE): from ||Z - q Q||^2 (EV_COEF) or pixel by
-// pixel over the block's own pixels (EV_SPATIAL).
-template <int CO, bool RECON, int EV>
-__device__ __forceinline__ uint64_t quant_block(const Plane& P, const s16x2 (&v)[8][8], int h,
-                                                const QuantConsts& qc, const ScaleConsts& sc,
-                                                int64_t t, const uint32_t (&a)[16], int x0,
-                                                int y0) {
-  constexpr bool ERR = (EV == EV_COEF);
-  constexpr bool INV = RECON || (EV == EV_SPATIAL);
-  double w[8][8];
-  double err = 0.0;
-  quant_rows<CO, INV, ERR>(v, h, qc, sc, P.coef, t, w, err, std::make_integer_sequence<int, 8>{});
-  if constexpr (INV) {
-    pass2d<double, false>(w);
-    const double sh = (double)P.shift;
+// Inverse of the quantisation path for block h: A' = C0^T S (q . Q) S C0 + shift.
+// The column pass (over k) is exact integer arithmetic grouped by the three
+// values of s_k: with Z = q Q, column l gives p = Z0 + Z4 and m = Z0 - Z4
+// (s = 1/sqrt8), Z2 and Z6 (s = 1/2), and the odd combinations b0..b3 of
+// Z1, Z3, Z5, Z7 (s = 1/sqrt6) -- the transposed flow graph without its last
+// stage.  Rows i and 7 - i of C0^T S Z are then a_i +- b_i with
+// a_i = {p or m}/sqrt8 +- {Z2 or Z6}/2 and b_i = b_i/sqrt6; scaled by s_l they
+// feed the float64 row pass.  Only 64 int32 values and two float64 rows are live.
+template <bool RECON, bool SP, bool FULL>
+__device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8][8], int h,
+                                              const QuantConsts& qc, const ScaleConsts& sc,
+                                              const uint32_t (&a)[16], int x0, int y0,
+                                              double& err) {
+  int cp[8], cm[8], c2[8], c6[8], cb[4][8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+  for (int l = 0; l < 8; ++l) {
+    int z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = __mul24(half(v[k][l], h), qc.qi[k * 8 + l]);
+    cp[l] = z[0] + z[4];
+    cm[l] = z[0] - z[4];
+    c2[l] = z[2];
+    c6[l] = z[6];
+    cb[0][l] = z[1] + (z[3] + z[5]);
+    cb[1][l] = z[1] - (z[5] + z[7]);
+    cb[2][l] = (z[1] + z[7]) - z[3];
+    cb[3][l] = z[5] - (z[3] + z[7]);
+  }
+  const double sh = (double)P.shift;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double up[8], um[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int e8 = (i == 0 || i == 3) ? cp[l] : cm[l];
+      const int e4 = (i == 0 || i == 3) ? c2[l] : c6[l];
+      const double s4 = (i == 0 || i == 2) ? sc.ss[16 + l] : -sc.ss[16 + l];
+      const double al = __builtin_fma((double)e4, s4, (double)e8 * sc.ss[l]);
+      const double be = (double)cb[i][l] * sc.ss[8 + l];
+      up[l] = al + be;
+      um[l] = al - be;
+    }
+    c0_transpose(up);
+    c0_transpose(um);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int row = side ? 7 - i : i;
+      const double (&o)[8] = side ? um : up;
       if constexpr (RECON) {
         float px[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) px[j] = (float)(w[i][j] + sh);
-        store_row(P, x0, y0 + i, px);
+        for (int j = 0; j < 8; ++j) px[j] = (float)(o[j] + sh);
+        if constexpr (FULL)
+          store_row_full(P, x0, y0 + row, px);
+        else
+          store_row(P, x0, y0 + row, px);
       }
-      if constexpr (EV == EV_SPATIAL) {
-        const bool row_ok = y0 + i < P.height;
+      if constexpr (SP) {
+        const bool row_ok = y0 + row < P.height;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const double e = (double)pixel(a, i, j) - (w[i][j] + sh);
+          const double e = (double)pixel(a, row, j) - (o[j] + sh);
           const double ed = (row_ok && x0 + j < P.width) ? e : 0.0;
           err = __builtin_fma(ed, ed, err);
         }
       }
     }
   }
+}
+
+// Quantisation path for block h of the pair: q = round(z / Q) exactly, staged for
+// output as it is produced; then the inverse.  Returns round(2^20 * block SSE):
+// from ||Z - q Q||^2 (EV_COEF) or pixel by pixel over the block's own pixels
+// (EV_SPATIAL).
+template <int CO, bool RECON, int EV>
+__device__ __forceinline__ uint64_t quant_block(const Plane& P, s16x2 (&v)[8][8], int h,
+                                                const QuantConsts& qc, const ScaleConsts& sc,
+                                                uint8_t* stage, const uint32_t (&a)[16], int x0,
+                                                int y0) {
+  constexpr bool ERR = (EV == EV_COEF);
+  constexpr bool SP = (EV == EV_SPATIAL);
+  double err = 0.0;
+  quant_rows<CO, ERR>(v, h, qc, sc, stage, err, std::make_integer_sequence<int, 8>{});
+  // EV_COEF is only used for planes made of whole blocks.
+  if constexpr (RECON || SP) quant_inverse<RECON, SP, EV == EV_COEF>(P, v, h, qc, sc, a, x0, y0, err);
   return (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
 }
 
@@ -380,32 +482,57 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t s) {
 // ---------------------------------------------------------------------------
 // One wave, one chunk of 128 blocks.
 // ---------------------------------------------------------------------------
-template <int SEL, int CO, bool RECON, int EV>
-__device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& qc,
-                                            const ScaleConsts& sc, int t0, int lane,
-                                            uint32_t* lds_wave) {
-  const int tl = t0 + lane, th = t0 + 64 + lane;
-  const bool vl = tl < P.nblocks, vh = th < P.nblocks;
+// Pixels of one chunk as loaded by a lane: blocks t0 + lane (lo) and
+// t0 + 64 + lane (hi).
+struct Pixels {
   uint32_t al[16], ah[16];
   int xl, yl, xh, yh;
-  load_block(P, tl, vl, al, xl, yl);
-  load_block(P, th, vh, ah, xh, yh);
+  int t0;
+  bool vl, vh;
+};
+
+__device__ __forceinline__ void chunk_load(const Plane& P, int t0, int lane, Pixels& px) {
+  px.t0 = t0;
+  px.vl = t0 + lane < P.nblocks;
+  px.vh = t0 + 64 + lane < P.nblocks;
+  load_block(P, t0 + lane, px.vl, px.al, px.xl, px.yl);
+  load_block(P, t0 + 64 + lane, px.vh, px.ah, px.xh, px.yh);
+}
+
+template <int SEL, int CO, bool RECON, int EV>
+__device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& qc,
+                                            const ScaleConsts& sc, const Pixels& px, int lane,
+                                            uint32_t* lds_wave, uint8_t* stage_wave) {
+  const int t0 = px.t0;
+  const int tl = t0 + lane, th = t0 + 64 + lane;
+  const bool vl = px.vl, vh = px.vh;
+  const int xl = px.xl, yl = px.yl, xh = px.xh, yh = px.yh;
+  const uint32_t (&al)[16] = px.al;
+  const uint32_t (&ah)[16] = px.ah;
 
   s16x2 v[8][8];
   forward_pair(al, ah, P.shift, v);
 
   if constexpr (SEL == SEL_Q) {
     uint64_t s = 0;
+    uint8_t* my_stage = stage_wave + lane * Stage<CO>::stride;
     // One block of the pair at a time keeps a single 8x8 inverse live.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      if (!(h ? vh : vl)) continue;
-      uint32_t a[16];
-      if constexpr (EV == EV_SPATIAL) {
+      if (h ? vh : vl) {
+        uint32_t a[16];
+        if constexpr (EV == EV_SPATIAL) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
+          for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
+        }
+        s += quant_block<CO, RECON, EV>(P, v, h, qc, sc, my_stage, a, h ? xh : xl, h ? yh : yl);
       }
-      s += quant_block<CO, RECON, EV>(P, v, h, qc, sc, h ? th : tl, a, h ? xh : xl, h ? yh : yl);
+      if constexpr (CO != CO_NONE) {
+        const int first = t0 + 64 * h;
+        wave_sync();
+        flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), lane);
+        wave_sync();
+      }
     }
     if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
       s = wave_sum_u64(s);
@@ -416,16 +543,21 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& q
   } else {
   const uint64_t keep = P.keep;
   if constexpr (CO != CO_NONE) {
+    uint8_t* my_stage = stage_wave + lane * Stage<CO>::stride;
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      const int t = h ? th : tl;
-      if (!(h ? vh : vl)) continue;
-      if constexpr (CO == CO_I32)
-        store_i32(reinterpret_cast<int32_t*>(P.coef) + (int64_t)t * 64, v, keep, h);
-      else if constexpr (CO == CO_I16)
-        store_i16(reinterpret_cast<int16_t*>(P.coef) + (int64_t)t * 64, v, keep, h);
-      else
-        store_f32(reinterpret_cast<float*>(P.coef) + (int64_t)t * 64, v, keep, sc, h);
+      if (h ? vh : vl) {
+        if constexpr (CO == CO_I32)
+          store_i32(reinterpret_cast<int32_t*>(my_stage), v, keep, h);
+        else if constexpr (CO == CO_I16)
+          store_i16(reinterpret_cast<int16_t*>(my_stage), v, keep, h);
+        else
+          store_f32(reinterpret_cast<float*>(my_stage), v, keep, sc, h);
+      }
+      const int first = t0 + 64 * h;
+      wave_sync();
+      flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), lane);
+      wave_sync();
     }
   }
 
@@ -457,16 +589,12 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& q
       const int y1v = vh ? (int)v[kl >> 3][kl & 7].y : 0;
       lds_wave[lane * 65 + kl] = (uint32_t)(y0v * y0v) + (uint32_t)(y1v * y1v);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
     const int pos = c_zz.order[lane];
     uint64_t e = 0;
 #pragma unroll 8
     for (int j = 0; j < 64; ++j) e += lds_wave[j * 65 + pos];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
     // Weighted energy d'_k d'_l sum Y^2 at rank `lane`, then suffix sums over rank:
     // the dropped energy when the first rho coefficients are kept.
     uint64_t x = e * (uint64_t)(kDp[pos >> 3] * kDp[pos & 7]);
@@ -482,24 +610,39 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& q
   }
 }
 
-// Register budget: the float64 reconstruction of the quantisation path keeps a
-// whole 8x8 float64 block live and is given a full wave-per-SIMD budget; every
-// other variant runs two waves per SIMD.
-template <int SEL, bool RECON, int EV>
+// Register budget: two waves per SIMD, except the quantisation variants that
+// keep pixels live for a pixel-domain error (planes with partial blocks) or
+// stage int32 coefficients beside the reconstruction; those get a full
+// wave-per-SIMD budget instead of spilling.
+template <int SEL, int CO, bool RECON, int EV>
 struct WideRegs {
-  static constexpr bool value = (SEL == SEL_Q) && (RECON || EV == EV_SPATIAL);
+  static constexpr bool value =
+      (SEL == SEL_Q) && (EV == EV_SPATIAL || (RECON && CO == CO_I32));
+};
+
+// Persistent batch kernels: prefetching the next work item costs ~40 registers;
+// it is used where the kernel is a pure stream (transform, quantise, store).
+// Kernels that also invert keep a float64 or int32 block live and run without it.
+template <int SEL, bool RECON, int EV>
+struct Prefetch {
+  static constexpr bool value = !RECON && (EV == EV_NONE || EV == EV_COEF || EV == EV_SWEEP);
 };
 
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void plane_kernel_body(const Plane& P, const QuantConsts& qc,
                                                   const ScaleConsts& sc) {
+  // One chunk of 128 blocks per wave; the grid covers the plane.
   extern __shared__ uint32_t lds[];
+  const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int chunk = blockIdx.x * (blockDim.x >> 6) + wave;
-  const int t0 = chunk * 128;
-  if (t0 >= P.nblocks) return;
-  plane_chunk<SEL, CO, RECON, EV>(P, qc, sc, t0, lane, lds + wave * (64 * 65));
+  const int c = blockIdx.x * wpg + wave;
+  if (c * 128 >= P.nblocks) return;
+  uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
+                   wave * Stage<CO>::wave_bytes;
+  Pixels cur;
+  chunk_load(P, c * 128, lane, cur);
+  plane_chunk<SEL, CO, RECON, EV>(P, qc, sc, cur, lane, lds + wave * (64 * 65), stage);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
@@ -526,10 +669,39 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int n_waves = gridDim.x * wpg;
-  for (int it = blockIdx.x * wpg + wave; it < n_items; it += n_waves) {
-    const WorkItem w = items[it];
-    const Plane& P = planes[w.plane];
-    plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, w.t0, lane, lds + wave * (64 * 65));
+  uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
+                   wave * Stage<CO>::wave_bytes;
+  uint32_t* sweep = lds + wave * (64 * 65);
+  int it = blockIdx.x * wpg + wave;
+  if (it >= n_items) return;
+  if constexpr (Prefetch<SEL, RECON, EV>::value) {
+    WorkItem w = items[it];
+    Pixels cur;
+    chunk_load(planes[w.plane], w.t0, lane, cur);
+    for (;;) {
+      const int itn = it + n_waves;
+      const bool more = itn < n_items;
+      WorkItem wn = w;
+      Pixels nxt;
+      if (more) {
+        wn = items[itn];
+        chunk_load(planes[wn.plane], wn.t0, lane, nxt);
+      }
+      const Plane& P = planes[w.plane];
+      plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, cur, lane, sweep, stage);
+      if (!more) break;
+      cur = nxt;
+      w = wn;
+      it = itn;
+    }
+  } else {
+    for (; it < n_items; it += n_waves) {
+      const WorkItem w = items[it];
+      const Plane& P = planes[w.plane];
+      Pixels cur;
+      chunk_load(P, w.t0, lane, cur);
+      plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, cur, lane, sweep, stage);
+    }
   }
 }
 
@@ -658,8 +830,9 @@ static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, const Sc
                                  int wpg, hipStream_t s) {
   const int chunks = (P.nblocks + 127) / 128;
   const int grid = (chunks + wpg - 1) / wpg;
-  const size_t lds = (EV == EV_SWEEP) ? (size_t)wpg * 64 * 65 * 4 : 0;
-  if constexpr (WideRegs<SEL, RECON, EV>::value)
+  const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
+                     (size_t)wpg * Stage<CO>::wave_bytes;
+  if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_plane_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
   else
     hipLaunchKernelGGL((k_plane<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
@@ -670,8 +843,9 @@ template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
                                  const ScaleConsts* scp, const WorkItem* items, int n_items,
                                  int grid, int wpg, hipStream_t s) {
-  const size_t lds = (EV == EV_SWEEP) ? (size_t)wpg * 64 * 65 * 4 : 0;
-  if constexpr (WideRegs<SEL, RECON, EV>::value)
+  const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
+                     (size_t)wpg * Stage<CO>::wave_bytes;
+  if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
                        tables, scp, items, n_items);
   else

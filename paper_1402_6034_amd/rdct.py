@@ -87,13 +87,36 @@ def lib() -> ctypes.CDLL:
     return L
 
 
+class PlaneDesc(ctypes.Structure):
+    """rdct_plane_desc_t."""
+    _fields_ = [("src", c_void_p), ("width", c_int32), ("height", c_int32),
+                ("src_pitch", c_int64), ("sel", Select), ("coef_out", c_void_p),
+                ("recon_out", c_void_p), ("recon_pitch", c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    """rdct_tuning_t."""
+    _fields_ = [("waves_per_wg", c_int32), ("wgs_per_cu", c_int32), ("use_graph", c_int32),
+                ("reserved", c_int32)]
+
+
 def _declare_extra(L):
-    """Signatures of the batch, server and tuning entry points (if present)."""
-    try:
-        from . import rdct_ext
-    except ImportError:  # pragma: no cover
-        return
-    rdct_ext.declare(L)
+    """Signatures of the batch and server entry points."""
+    P = c_void_p
+    L.rdct_batch_plan_create.argtypes = [POINTER(PlaneDesc), c_int32, c_int32, P,
+                                         POINTER(Tuning), POINTER(c_void_p)]
+    L.rdct_batch_plan_create.restype = c_int32
+    L.rdct_batch_run.argtypes = [P, P]
+    L.rdct_batch_run.restype = c_int32
+    L.rdct_batch_plan_info.argtypes = [P, POINTER(c_int64), POINTER(c_int32), POINTER(Tuning)]
+    L.rdct_batch_plan_info.restype = c_int32
+    L.rdct_batch_autotune.argtypes = [P, c_int32, P, POINTER(Tuning)]
+    L.rdct_batch_autotune.restype = c_int32
+    L.rdct_batch_plan_destroy.argtypes = [P]
+    L.rdct_batch_plan_destroy.restype = None
+    if hasattr(L, "rdct_server_create"):
+        from . import serve as _serve
+        _serve.declare(L)
 
 
 def _check(status: int, what: str):
@@ -210,3 +233,100 @@ def compress_eval(img: torch.Tensor, sel: Select, r_count: int = 1, coef_type: i
 
 def psnr_from_sse(sse_raw: int, mode: int, height: int, width: int) -> float:
     return rdct_psnr(int(sse_raw), mode, width, height)
+
+
+# ---------------------------------------------------------------------------
+# Batch plans (one persistent launch over many planes)
+# ---------------------------------------------------------------------------
+
+def rdct_batch_plan_create(descs, n, coef_type, sse_out, tuning=None):
+    h = c_void_p()
+    _check(lib().rdct_batch_plan_create(descs, n, coef_type, _ptr(sse_out),
+                                        ctypes.byref(tuning) if tuning is not None else None,
+                                        ctypes.byref(h)), "rdct_batch_plan_create")
+    return h
+
+
+def rdct_batch_run(plan, stream=None):
+    _check(lib().rdct_batch_run(plan, _stream(stream)), "rdct_batch_run")
+
+
+def rdct_batch_plan_info(plan):
+    nb, ni, t = c_int64(), c_int32(), Tuning()
+    _check(lib().rdct_batch_plan_info(plan, ctypes.byref(nb), ctypes.byref(ni), ctypes.byref(t)),
+           "rdct_batch_plan_info")
+    return nb.value, ni.value, t
+
+
+def rdct_batch_autotune(plan, reps=5, stream=None):
+    t = Tuning()
+    _check(lib().rdct_batch_autotune(plan, reps, _stream(stream), ctypes.byref(t)),
+           "rdct_batch_autotune")
+    return t
+
+
+def rdct_batch_plan_destroy(plan):
+    lib().rdct_batch_plan_destroy(plan)
+
+
+class BatchPlan:
+    """A batch of device planes with their selections; outputs are allocated here
+    (coefficients and reconstructions as slices of two flat buffers) and stay
+    resident.  `run()` launches the whole batch; `sse` holds one raw error sum
+    per plane (see rdct_sse_unit)."""
+
+    def __init__(self, planes, sels, coef_type=None, recon=False, tuning=None, device=None):
+        if len(planes) != len(sels) or not planes:
+            raise ValueError("planes and selections must be non-empty and equal in number")
+        dev = planes[0].device if device is None else device
+        self.planes, self.sels = list(planes), list(sels)
+        self.n = len(planes)
+        self.shapes = [tuple(p.shape) for p in planes]
+        nbs = [rdct_num_blocks(w, h) for (h, w) in self.shapes]
+        self.coef = self.recon = None
+        self.coef_views, self.recon_views = [None] * self.n, [None] * self.n
+        if coef_type is not None:
+            self.coef = torch.empty(sum(nbs) * 64, dtype=_TORCH_DTYPE[coef_type], device=dev)
+            off = 0
+            for i, nb in enumerate(nbs):
+                self.coef_views[i] = self.coef[off:off + nb * 64].view(nb, 64)
+                off += nb * 64
+        if recon:
+            tot = sum(h * w for (h, w) in self.shapes)
+            self.recon = torch.empty(tot, dtype=torch.float32, device=dev)
+            off = 0
+            for i, (h, w) in enumerate(self.shapes):
+                self.recon_views[i] = self.recon[off:off + h * w].view(h, w)
+                off += h * w
+        self.sse = torch.zeros(self.n, dtype=torch.int64, device=dev)
+        descs = (PlaneDesc * self.n)()
+        for i, (img, sel) in enumerate(zip(self.planes, self.sels)):
+            w, h, pitch = _plane_args(img)
+            d = descs[i]
+            d.src, d.width, d.height, d.src_pitch = img.data_ptr(), w, h, pitch
+            d.sel = sel
+            d.coef_out = self.coef_views[i].data_ptr() if self.coef is not None else None
+            d.recon_out = self.recon_views[i].data_ptr() if recon else None
+            d.recon_pitch = w if recon else 0
+        self._descs = descs
+        self.coef_type = COEF_I32 if coef_type is None else coef_type
+        self.handle = rdct_batch_plan_create(descs, self.n, self.coef_type, self.sse, tuning)
+        self.n_blocks, self.n_items, self.tuning = rdct_batch_plan_info(self.handle)
+
+    def run(self, stream=None):
+        rdct_batch_run(self.handle, stream)
+
+    def autotune(self, reps=5, stream=None):
+        self.tuning = rdct_batch_autotune(self.handle, reps, stream)
+        return self.tuning
+
+    def close(self):
+        if self.handle:
+            rdct_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -109,3 +109,28 @@ def test_inverse_rejects():
     assert L.rdct_inverse(FAKE_SRC, R.COEF_I32, 8, 8, ctypes.byref(sel), FAKE_DST, 4, None) == R.ERR_INVALID_ARG
     qs = R.select(R.SEL_QUANT, quality=50)
     assert L.rdct_inverse(FAKE_SRC, R.COEF_F32, 8, 8, ctypes.byref(qs), FAKE_DST, 8, None) == R.ERR_INVALID_ARG
+
+
+@needs_no_gpu
+def test_batch_plan_create_rejects():
+    L = R.lib()
+    h = ctypes.c_void_p()
+
+    def desc(mode, **kw):
+        d = R.PlaneDesc()
+        d.src, d.width, d.height, d.src_pitch = FAKE_SRC, 64, 64, 64
+        d.sel = R.select(mode, r=10, quality=50)
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+    arr = (R.PlaneDesc * 2)(desc(R.SEL_QUANT), desc(R.SEL_ZIGZAG))
+    assert L.rdct_batch_plan_create(arr, 2, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    arr = (R.PlaneDesc * 2)(desc(R.SEL_QUANT), desc(R.SEL_QUANT, coef_out=FAKE_DST))
+    assert L.rdct_batch_plan_create(arr, 2, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_QUANT, width=0))
+    assert L.rdct_batch_plan_create(arr, 1, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_QUANT))
+    assert L.rdct_batch_plan_create(arr, 1, R.COEF_I16, None, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    assert L.rdct_batch_plan_create(arr, 0, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    assert L.rdct_batch_run(None, None) == R.ERR_INVALID_ARG
+    assert L.rdct_batch_autotune(None, 3, None, None) == R.ERR_INVALID_ARG

@@ -1,0 +1,127 @@
+"""Batch plans: each plane's result inside a ragged batch equals its result alone
+(bit-exact: same kernels, integer reductions), and equals the oracle; captured
+graphs give the same result on every replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1402_6034_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+R = pytest.importorskip("paper_1402_6034_amd.rdct")
+DEV = "cuda:0"
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def ragged_planes(n, seed, full_blocks=True):
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for i in range(n):
+        h, w = int(rng.integers(1, 40)) * 8, int(rng.integers(1, 40)) * 8
+        if not full_blocks and i % 3 == 0:
+            h, w = h - int(rng.integers(0, 7)), w - int(rng.integers(0, 7))
+        shapes.append((h, w))
+    imgs = [synth.render_np(1000 * seed + i, h, w) for i, (h, w) in enumerate(shapes)]
+    return imgs, [torch.from_numpy(a).to(DEV) for a in imgs], rng
+
+
+@pytest.mark.parametrize("full", [True, False])
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_quant_batch_equals_single_and_oracle(full, use_graph):
+    imgs, dev, rng = ragged_planes(23, 1, full)
+    quals = [int(q) for q in rng.integers(10, 91, size=len(imgs))]
+    sels = [R.select(R.SEL_QUANT, quality=q, level_shift=128) for q in quals]
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(1, 4, use_graph, 0))
+    plan.run()
+    sse = host(plan.sse)
+    for i, (img, d, sel) in enumerate(zip(imgs, dev, sels)):
+        s1, c1, r1 = R.compress_eval(d, sel, 1, R.COEF_I16, True)
+        assert int(host(s1)[0]) == int(sse[i]), i
+        assert np.array_equal(host(c1), host(plan.coef_views[i])), i
+        assert np.array_equal(host(r1), host(plan.recon_views[i])), i
+    for i in (0, 5, 11):
+        ref = O.quant_eval(imgs[i], O.quant_table(quals[i]))
+        assert np.array_equal(host(plan.coef_views[i]).astype(np.int64), ref["q"].reshape(-1, 64))
+        assert np.max(np.abs(host(plan.recon_views[i]) - ref["recon"])) <= 1e-4
+        h, w = imgs[i].shape
+        assert abs(R.psnr_from_sse(int(sse[i]), R.SEL_QUANT, h, w) - ref["psnr"]) <= 1e-3
+    plan.close()
+
+
+def test_retention_batch_equals_single_and_oracle():
+    imgs, dev, rng = ragged_planes(17, 2, full_blocks=False)
+    rs = [int(r) for r in rng.integers(1, 46, size=len(imgs))]
+    sels = [R.select(R.SEL_ZIGZAG, r=r) for r in rs]
+    plan = R.BatchPlan(dev, sels, R.COEF_I32, recon=True)
+    plan.run()
+    sse = host(plan.sse)
+    for i, (img, d, sel) in enumerate(zip(imgs, dev, sels)):
+        s1, c1, r1 = R.compress_eval(d, sel, 1, R.COEF_I32, True)
+        assert int(host(s1)[0]) == int(sse[i])
+        assert np.array_equal(host(c1), host(plan.coef_views[i]))
+        assert np.array_equal(host(r1), host(plan.recon_views[i]))
+        ref = O.retention_eval(img, [rs[i]])
+        assert int(sse[i]) == ref["sse_num"][rs[i]]
+    plan.close()
+
+
+def test_graph_replays_are_identical():
+    imgs, dev, rng = ragged_planes(9, 3)
+    sels = [R.select(R.SEL_QUANT, quality=int(q), level_shift=128) for q in rng.integers(10, 91, 9)]
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(1, 2, 1, 0))
+    plan.run()
+    ref = (host(plan.sse).copy(), host(plan.coef).copy(), host(plan.recon).copy())
+    for k in range(4):
+        # Eager work between replays: scribble over the outputs.
+        plan.coef.fill_(-7)
+        plan.recon.fill_(float("nan"))
+        plan.sse.fill_(123456789)
+        torch.cuda.synchronize()
+        plan.run()
+        assert np.array_equal(host(plan.sse), ref[0]), k
+        assert np.array_equal(host(plan.coef), ref[1]), k
+        assert np.array_equal(host(plan.recon), ref[2]), k
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    monkeypatch.setenv("RDCT_TUNING_CACHE", str(tmp_path / "tune.json"))
+    imgs, dev, rng = ragged_planes(12, 4)
+    sels = [R.select(R.SEL_QUANT, quality=50, level_shift=128) for _ in imgs]
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True)
+    plan.run()
+    before = host(plan.sse).copy()
+    t = plan.autotune(reps=2)
+    assert t.waves_per_wg in (1, 2, 4) and 1 <= t.wgs_per_cu <= 16
+    plan.run()
+    assert np.array_equal(host(plan.sse), before)
+    text = (tmp_path / "tune.json").read_text()
+    assert '"waves_per_wg"' in text and "gfx950/batch" in text
+    # A new plan of the same class picks the cached geometry.
+    plan2 = R.BatchPlan(dev, sels, R.COEF_I16, recon=True)
+    assert (plan2.tuning.waves_per_wg, plan2.tuning.wgs_per_cu) == (t.waves_per_wg, t.wgs_per_cu)
+    plan.close()
+    plan2.close()
+
+
+def test_batch_of_one_full_hd_plane_and_tiny_planes():
+    shapes = [(1080, 1920), (8, 8), (1, 1), (13, 7)]
+    imgs = [synth.render_np(50 + i, h, w) for i, (h, w) in enumerate(shapes)]
+    dev = [torch.from_numpy(a).to(DEV) for a in imgs]
+    sels = [R.select(R.SEL_ZIGZAG, r=r) for r in (10, 1, 64, 3)]
+    plan = R.BatchPlan(dev, sels, None, recon=False)
+    plan.run()
+    sse = host(plan.sse)
+    for i, img in enumerate(imgs):
+        r = sels[i].r
+        s1, _, _ = R.compress_eval(dev[i], sels[i], 1)
+        assert int(host(s1)[0]) == int(sse[i])
+    ref = O.retention_eval(imgs[3], [3])
+    assert int(sse[3]) == ref["sse_num"][3]
+    plan.close()
