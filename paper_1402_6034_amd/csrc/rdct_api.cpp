@@ -28,14 +28,13 @@ void fill_quant_consts(const uint16_t q[64], QuantConsts* out) {
       const double m = 1.0 / (Q * sqrt(gg));
       memcpy(&out->qm[kl], &m, 8);
     }
-    out->dq[kl] = Q / sqrt(gg);
+    out->dq[kl] = Q * scale_kl(k, l);
     out->qi[kl] = (int32_t)q[kl];
   }
 }
 
 void fill_scale_consts(ScaleConsts* out) {
-  for (int kl = 0; kl < 64; ++kl)
-    out->ss[kl] = 1.0 / sqrt((double)kGram[kl >> 3] * (double)kGram[kl & 7]);
+  for (int kl = 0; kl < 64; ++kl) out->ss[kl] = scale_kl(kl >> 3, kl & 7);
 }
 
 uint64_t keep_bits(int r) {

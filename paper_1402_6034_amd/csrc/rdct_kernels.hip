@@ -24,8 +24,17 @@
 namespace rdct {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// Pointers read from descriptors are generic; casting them to the global
+// address space lets the compiler emit global (not flat) memory instructions.
+#define RDCT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RDCT_GLOBAL T* gptr(T* p) {
+  return (RDCT_GLOBAL T*)p;
+}
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __constant__ ZigZag c_zz = make_zigzag();
 
@@ -129,11 +138,11 @@ __device__ __forceinline__ void load_block(const Plane& P, int t, bool valid, ui
   x0 = bx * 8;
   y0 = by * 8;
   if (P.aligned8 && x0 + 8 <= P.width && y0 + 8 <= P.height) {
-    const uint8_t* base = P.src + (int64_t)y0 * P.pitch + x0;
+    const RDCT_GLOBAL uint8_t* base = gptr(P.src) + (int64_t)y0 * P.pitch + x0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const u32x2 r = __builtin_nontemporal_load(
-          reinterpret_cast<const u32x2*>(base + (int64_t)i * P.pitch));
+          reinterpret_cast<const RDCT_GLOBAL u32x2*>(base + (int64_t)i * P.pitch));
       w[2 * i] = r.x;
       w[2 * i + 1] = r.y;
     }
@@ -141,7 +150,7 @@ __device__ __forceinline__ void load_block(const Plane& P, int t, bool valid, ui
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int y = min(y0 + i, P.height - 1);
-      const uint8_t* row = P.src + (int64_t)y * P.pitch;
+      const RDCT_GLOBAL uint8_t* row = gptr(P.src) + (int64_t)y * P.pitch;
       uint32_t d0 = 0, d1 = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -231,7 +240,7 @@ __device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], ui
     float e[8];
 #pragma unroll
     for (int l = 0; l < 8; ++l)
-      e[l] = ((keep >> (k * 8 + l)) & 1) ? (float)((double)half(v[k][l], h) * sc.ss[k * 8 + l])
+      e[l] = ((keep >> (k * 8 + l)) & 1) ? (float)((double)half(v[k][l], h) * scale_kl(k, l))
                                          : 0.0f;
     reinterpret_cast<float4*>(out)[2 * k] = make_float4(e[0], e[1], e[2], e[3]);
     reinterpret_cast<float4*>(out)[2 * k + 1] = make_float4(e[4], e[5], e[6], e[7]);
@@ -241,18 +250,18 @@ __device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], ui
 // Store one reconstructed row of 8 pixels of a block that lies inside the plane,
 // on a plane whose rows are 16-byte aligned (checked on the host).
 __device__ __forceinline__ void store_row_full(const Plane& P, int x0, int y, const float (&px)[8]) {
-  float* row = P.recon + (int64_t)y * P.rpitch + x0;
-  reinterpret_cast<float4*>(row)[0] = make_float4(px[0], px[1], px[2], px[3]);
-  reinterpret_cast<float4*>(row)[1] = make_float4(px[4], px[5], px[6], px[7]);
+  RDCT_GLOBAL float* row = gptr(P.recon) + (int64_t)y * P.rpitch + x0;
+  reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[0] = (f32x4){px[0], px[1], px[2], px[3]};
+  reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[1] = (f32x4){px[4], px[5], px[6], px[7]};
 }
 
 // Store one reconstructed row of 8 pixels (clipped to the plane).
 __device__ __forceinline__ void store_row(const Plane& P, int x0, int y, const float (&px)[8]) {
   if (y >= P.height) return;
-  float* row = P.recon + (int64_t)y * P.rpitch + x0;
+  RDCT_GLOBAL float* row = gptr(P.recon) + (int64_t)y * P.rpitch + x0;
   if (x0 + 8 <= P.width && ((reinterpret_cast<uintptr_t>(row) & 15u) == 0)) {
-    reinterpret_cast<float4*>(row)[0] = make_float4(px[0], px[1], px[2], px[3]);
-    reinterpret_cast<float4*>(row)[1] = make_float4(px[4], px[5], px[6], px[7]);
+    reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[0] = (f32x4){px[0], px[1], px[2], px[3]};
+    reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[1] = (f32x4){px[4], px[5], px[6], px[7]};
   } else {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
@@ -289,7 +298,7 @@ __device__ __forceinline__ void flush_stage(const uint8_t* stage, void* coef, in
                                             int nvalid, int lane) {
   constexpr int per_block = Stage<CO>::bytes / 16;   // 16-byte pieces per block
   constexpr int pieces = 64 * per_block;
-  uint8_t* out = reinterpret_cast<uint8_t*>(coef) + t_first * Stage<CO>::bytes;
+  RDCT_GLOBAL uint8_t* out = gptr(reinterpret_cast<uint8_t*>(coef)) + t_first * Stage<CO>::bytes;
   const int limit = nvalid * per_block;
 #pragma unroll
   for (int m = 0; m < pieces / 64; ++m) {
@@ -297,7 +306,7 @@ __device__ __forceinline__ void flush_stage(const uint8_t* stage, void* coef, in
     const int b = c / per_block, o = c - b * per_block;
     if (c < limit) {
       const u32x4 val = *reinterpret_cast<const u32x4*>(stage + b * Stage<CO>::stride + o * 16);
-      __builtin_nontemporal_store(val, reinterpret_cast<u32x4*>(out + (int64_t)c * 16));
+      __builtin_nontemporal_store(val, reinterpret_cast<RDCT_GLOBAL u32x4*>(out + (int64_t)c * 16));
     }
   }
 }
@@ -359,7 +368,7 @@ __device__ __forceinline__ void quant_row(s16x2 (&row)[8], int h, const QuantCon
     q[l] = qq;
     if constexpr (ERR) {
       // z - q Q with z = s_k s_l Y: one rounding (FMA) per coefficient.
-      const double d = __builtin_fma((double)y, sc.ss[kl], -(double)__mul24(qq, qc.qi[kl]));
+      const double d = __builtin_fma((double)y, scale_kl(kl >> 3, kl & 7), -(double)__mul24(qq, qc.qi[kl]));
       err = __builtin_fma(d, d, err);
     }
     row[l] = as_pair(__builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, row[l]), (uint32_t)qq, put));
@@ -404,6 +413,9 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
     int z[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = __mul24(half(v[k][l], h), qc.qi[k * 8 + l]);
+    // The level shift: adding 8 * shift to Z_00 adds shift to every pixel (the
+    // DC basis function of C_orth is 1/8 everywhere).
+    if (l == 0) z[0] += 8 * P.shift;
     cp[l] = z[0] + z[4];
     cm[l] = z[0] - z[4];
     c2[l] = z[2];
@@ -413,7 +425,6 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
     cb[2][l] = (z[1] + z[7]) - z[3];
     cb[3][l] = z[5] - (z[3] + z[7]);
   }
-  const double sh = (double)P.shift;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double up[8], um[8];
@@ -421,9 +432,9 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
     for (int l = 0; l < 8; ++l) {
       const int e8 = (i == 0 || i == 3) ? cp[l] : cm[l];
       const int e4 = (i == 0 || i == 3) ? c2[l] : c6[l];
-      const double s4 = (i == 0 || i == 2) ? sc.ss[16 + l] : -sc.ss[16 + l];
-      const double al = __builtin_fma((double)e4, s4, (double)e8 * sc.ss[l]);
-      const double be = (double)cb[i][l] * sc.ss[8 + l];
+      const double s4 = (i == 0 || i == 2) ? scale_kl(2, l) : -scale_kl(2, l);
+      const double al = __builtin_fma((double)e4, s4, (double)e8 * scale_kl(0, l));
+      const double be = (double)cb[i][l] * scale_kl(1, l);
       up[l] = al + be;
       um[l] = al - be;
     }
@@ -436,7 +447,7 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
       if constexpr (RECON) {
         float px[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) px[j] = (float)(o[j] + sh);
+        for (int j = 0; j < 8; ++j) px[j] = (float)o[j];
         if constexpr (FULL)
           store_row_full(P, x0, y0 + row, px);
         else
@@ -446,7 +457,7 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
         const bool row_ok = y0 + row < P.height;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const double e = (double)pixel(a, row, j) - (o[j] + sh);
+          const double e = (double)pixel(a, row, j) - o[j];
           const double ed = (row_ok && x0 + j < P.width) ? e : 0.0;
           err = __builtin_fma(ed, ed, err);
         }
@@ -781,7 +792,7 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
         const float z[8] = {u.x, u.y, u.z, u.w, s.x, s.y, s.z, s.w};
 #pragma unroll
         for (int l = 0; l < 8; ++l)
-          w[k][l] = ((keep >> (k * 8 + l)) & 1) ? (double)z[l] * sc.ss[k * 8 + l] : 0.0;
+          w[k][l] = ((keep >> (k * 8 + l)) & 1) ? (double)z[l] * scale_kl(k, l) : 0.0;
       }
     } else if constexpr (KIND == INV_Q_I32) {
       const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)t * 16;

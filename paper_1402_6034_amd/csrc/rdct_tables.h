@@ -23,6 +23,20 @@ constexpr int kDp[8] = {3, 4, 6, 4, 3, 4, 6, 4};
 // square root is g_k) or irrational.
 constexpr bool rational_pos(int k, int l) { return kGram[k] == kGram[l]; }
 
+// s_k s_l = 1 / sqrt(g_k g_l) in float64, as 1.0 / sqrt(double(g_k g_l)) rounds
+// it; g_k g_l takes six values (64, 48, 32, 36, 24, 16).  Hexadecimal literals
+// keep the values exact at compile time.
+constexpr double scale_kl(int k, int l) {
+  switch (kGram[k] * kGram[l]) {
+    case 64: return 0x1.0000000000000p-3;
+    case 48: return 0x1.279a74590331dp-3;
+    case 32: return 0x1.6a09e667f3bccp-3;
+    case 36: return 0x1.5555555555555p-3;
+    case 24: return 0x1.a20bd700c2c3fp-3;
+    default: return 0x1.0000000000000p-2;  // 16
+  }
+}
+
 struct ZigZag {
   int order[64];  // rank -> natural index
   int rank[64];   // natural index -> rank

@@ -16,7 +16,8 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_uint16, c_uint64, c_vo
 import torch  # noqa: F401  (loads the HIP runtime that the library shares)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librdct.so")
+# RDCT_LIB may name another build of the library (e.g. to compare kernel variants).
+LIB_PATH = os.environ.get("RDCT_LIB") or os.path.join(_HERE, "librdct.so")
 
 # rdct_status_t
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_MEMORY, ERR_BUDGET, ERR_NOT_FOUND, ERR_BUSY = range(8)
