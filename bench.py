@@ -266,6 +266,59 @@ class RaggedBatch:
                           "exact quantisation + float64 inverse + SSE"}
 
 
+def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
+    """Poisson trace of compression requests (Y + 4:2:0 Cb/Cr planes, resolutions
+    256x256 .. 3840x2160, r uniform in 1..45) replayed in real time against the
+    batching server and against the plain path (one synchronous launch per
+    plane); p50/p99 latency from arrival to completion, throughput, and whether
+    the two give identical error sums."""
+    import numpy as np
+    from paper_1402_6034_amd import rdct as R, serve as S, synth
+    trace = synth.serve_trace(0, n_requests, rate_hz, pool=pool)
+    planes = {}
+    for q in trace:
+        if q.seed not in planes:
+            ch, cw = synth.chroma_shape(q.height, q.width)
+            planes[q.seed] = [synth.render(q.seed, q.height, q.width, device="cuda").cpu().numpy(),
+                              synth.render(q.seed + 1, ch, cw, device="cuda").cpu().numpy(),
+                              synth.render(q.seed + 2, ch, cw, device="cuda").cpu().numpy()]
+    sels = [R.select(R.SEL_ZIGZAG, r=q.r) for q in trace]
+    idx = {id(q): i for i, q in enumerate(trace)}
+    out = {"requests": n_requests, "rate_hz": rate_hz, "budget_bytes": budget,
+           "mean_pixels_per_request": float(np.mean([sum(p.size for p in planes[q.seed]) for q in trace]))}
+    results = {}
+    blocks = sum(R.rdct_num_blocks(p.shape[1], p.shape[0]) for q in trace for p in planes[q.seed])
+    for name, plain in (("batched", False), ("plain", True)):
+        srv = S.Server(budget_bytes=budget, n_streams=2, plain=plain)
+        # Warm-up (kernel loading, first launches): one request per pool entry.
+        for k, key in enumerate(planes):
+            srv.submit(planes[key], sels[0], tag=10 ** 9 + k)
+        srv.drain(60000)
+        while srv.poll(256):
+            pass
+        res = {}
+        for mode, speed in (("trace", 1.0), ("burst", 1e9)):
+            done, wall, busy = S.replay(srv, trace, lambda q: planes[q.seed],
+                                        lambda q: sels[idx[id(q)]], timeout_s=300.0, speed=speed)
+            lat = S.latency_stats(done)
+            res[mode] = {"p50_ms": round(lat["p50_ms"], 4), "p99_ms": round(lat["p99_ms"], 4),
+                         "mean_ms": round(lat["mean_ms"], 4), "max_ms": round(lat["max_ms"], 4),
+                         "req_per_s": round(n_requests / wall, 1),
+                         "mblocks_per_s": round(blocks / wall / 1e6, 2), "busy_retries": busy}
+            if mode == "trace":
+                results[name] = done
+            log(f"[bench] serving {name} {mode}: p50 {lat['p50_ms']:.3f} ms, "
+                f"p99 {lat['p99_ms']:.3f} ms, {n_requests / wall:.0f} req/s")
+        st = srv.stats()
+        srv.close()
+        res["launches"] = st["batches"]
+        res["peak_device_bytes"] = st["peak_device_bytes"]
+        out[name] = res
+    out["identical_sse"] = all(results["batched"][i]["sse"] == results["plain"][i]["sse"]
+                               for i in range(n_requests))
+    return out
+
+
 WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch}
 
 
@@ -284,6 +337,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="ragged: use the tuning cache (or defaults) instead of tuning first")
+    ap.add_argument("--serve-requests", type=int, default=4000,
+                    help="requests in the served trace (2000 req/s; 0 = skip the serving leg)")
     ap.add_argument("--planes-cache", default=None,
                     help="ragged: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -343,6 +398,11 @@ def main():
         log("[bench] timing the plain one-launch-per-plane path")
         plain = wl.plain()
 
+    serving = None
+    if args.serve_requests > 0:
+        log("[bench] serving leg")
+        serving = serving_leg(args.serve_requests)
+
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mblocks/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -350,6 +410,8 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu}
     if plain is not None:
         out["plain"] = plain
+    if serving is not None:
+        out["serving"] = serving
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         n = args.calibrate_copy << 20

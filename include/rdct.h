@@ -50,7 +50,8 @@ typedef enum {
   RDCT_ERR_NO_MEMORY = 4,   /* plan / server creation could not allocate */
   RDCT_ERR_BUDGET = 5,      /* server: request larger than the whole device budget */
   RDCT_ERR_NOT_FOUND = 6,   /* server: unknown ticket */
-  RDCT_ERR_BUSY = 7         /* server: queue full (non-blocking submit) */
+  RDCT_ERR_BUSY = 7,        /* server: queue or staging full (non-blocking submit) */
+  RDCT_ERR_CANCELLED = 8    /* server: the request was cancelled before admission */
 } rdct_status_t;
 
 /* Element type of a coefficient buffer. */
@@ -211,6 +212,86 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
 
 /* Release the plan's device memory and graph (synchronises its internal stream). */
 void rdct_batch_plan_destroy(rdct_batch_plan_t* plan);
+
+/* ------------------------------------------------------------------------- */
+/* Compression server: admission by device-memory budget, continuous batching */
+/* ------------------------------------------------------------------------- */
+
+typedef struct rdct_server rdct_server_t;
+
+typedef struct {
+  int64_t budget_bytes;     /* device memory for admitted requests (planes, descriptors,
+                               error sums); the server allocates it once at creation     */
+  int64_t staging_bytes;    /* pinned host staging for submitted requests (0 = budget/4,
+                               at most 2 GiB)                                             */
+  int32_t max_inflight;     /* requests admitted and not yet completed (0 = 4096)         */
+  int32_t max_batch_planes; /* planes per launch (0 = 4096)                               */
+  int32_t n_streams;        /* device streams, batches in flight at once: 1..4 (0 = 2)    */
+  int32_t plain;            /* 1: no batching -- each plane runs alone (copy, launch,
+                               synchronise) in submission order; the comparison path      */
+} rdct_server_cfg_t;
+
+/* A request: 1..3 planes of one picture (e.g. Y, Cb, Cr of 4:2:0), all scored with
+   the same selection.  The planes are HOST pointers; submit copies them, so the
+   caller may reuse its buffers as soon as submit returns. */
+typedef struct {
+  const uint8_t* planes[3];
+  int32_t width[3], height[3];
+  int64_t pitch[3];         /* bytes per host row (>= width)                            */
+  int32_t n_planes;
+  rdct_select_t sel;        /* ZIGZAG (r) or QUANT; no coefficient output               */
+  uint64_t user_tag;
+} rdct_request_t;
+
+typedef struct {
+  uint64_t ticket;
+  uint64_t user_tag;
+  int32_t status;           /* RDCT_OK, RDCT_ERR_CANCELLED or RDCT_ERR_HIP              */
+  int32_t n_planes;
+  uint64_t sse[3];          /* raw error sums, units rdct_sse_unit(mode)                */
+  double psnr[3];           /* dB, +inf for an exact reconstruction                     */
+  double t_submit_us;       /* times in microseconds since the server was created       */
+  double t_launch_us;       /* when its batch was launched                               */
+  double t_done_us;         /* when the server saw the batch complete                    */
+  int32_t batch_planes;     /* planes in the launch that carried it                      */
+  int32_t reserved;
+} rdct_completion_t;
+
+typedef struct {
+  int64_t submitted, completed, cancelled, rejected;
+  int64_t batches, planes, blocks;
+  int64_t peak_device_bytes;   /* high-water mark of the budget in use */
+  int64_t device_bytes_in_use;
+  int32_t pending, inflight;
+} rdct_server_stats_t;
+
+/* Create a server (allocates the device budget and pinned staging; starts one
+   scheduler thread).  Errors: INVALID_ARG, NO_MEMORY, HIP. */
+rdct_status_t rdct_server_create(const rdct_server_cfg_t* cfg, rdct_server_t** out);
+
+/* Queue a request without blocking.  Errors: INVALID_ARG (bad plane or selection),
+   BUDGET (the request alone exceeds the device budget: it could never be admitted),
+   BUSY (staging full -- retry later). */
+rdct_status_t rdct_server_submit(rdct_server_t* srv, const rdct_request_t* req, uint64_t* ticket);
+
+/* Move up to `max` completions into out[]; waits up to wait_us microseconds for the
+   first one (0 = do not wait).  *n receives the count. */
+rdct_status_t rdct_server_poll(rdct_server_t* srv, rdct_completion_t* out, int32_t max,
+                               int32_t* n, int32_t wait_us);
+
+/* Cancel a request that has not been admitted yet: it completes with
+   RDCT_ERR_CANCELLED.  NOT_FOUND if the ticket is unknown, BUSY if already admitted. */
+rdct_status_t rdct_server_cancel(rdct_server_t* srv, uint64_t ticket);
+
+/* Block until every submitted request has completed (or timeout_ms passes:
+   RDCT_ERR_BUSY). */
+rdct_status_t rdct_server_drain(rdct_server_t* srv, int32_t timeout_ms);
+
+rdct_status_t rdct_server_stats(rdct_server_t* srv, rdct_server_stats_t* out);
+
+/* Stop the scheduler, wait for launched work, free everything.  Pending requests
+   are dropped. */
+void rdct_server_destroy(rdct_server_t* srv);
 
 const char* rdct_status_string(rdct_status_t status);
 

@@ -260,7 +260,8 @@ const char* rdct_status_string(rdct_status_t s) {
     case RDCT_ERR_NO_MEMORY: return "out of device memory";
     case RDCT_ERR_BUDGET: return "request exceeds the device-memory budget";
     case RDCT_ERR_NOT_FOUND: return "unknown ticket";
-    case RDCT_ERR_BUSY: return "queue full";
+    case RDCT_ERR_BUSY: return "busy: queue or staging full";
+    case RDCT_ERR_CANCELLED: return "cancelled";
     default: return "unknown status";
   }
 }

@@ -1,0 +1,622 @@
+// Compression server: requests of mixed resolutions are admitted against a
+// device-memory budget and scored in batches that run while new requests keep
+// arriving (continuous batching).
+//
+// Submit copies a request's planes into pinned host staging and queues it.  One
+// scheduler thread (a) retires launched batches whose event has fired, turning
+// their error sums into completions and freeing their memory, and (b) whenever a
+// stream is free, forms the next batch from the oldest pending requests that fit
+// in the device budget, and launches it: plane uploads, the descriptor upload,
+// the zeroing kernel, the persistent batch kernel and the read-back of the error
+// sums, all asynchronous on that stream, followed by an event.  Batches on
+// different streams overlap on the device.  The per-block arithmetic is the
+// same device code as the single-plane calls, so results do not depend on what
+// a request was batched with.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "rdct_internal.h"
+#include "rdct_tables.h"
+
+using namespace rdct;
+
+namespace {
+
+// First-fit allocator over [0, size) with a coalescing free list.
+class Arena {
+ public:
+  void reset(int64_t size, int64_t align) {
+    size_ = size;
+    align_ = align;
+    used_ = 0;
+    free_.clear();
+    if (size > 0) free_[0] = size;
+  }
+  int64_t alloc(int64_t bytes) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = round(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t in_use() const { return used_; }
+  int64_t round(int64_t b) const { return (b + align_ - 1) / align_ * align_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t size_ = 0, align_ = 256, used_ = 0;
+};
+
+struct PlaneSlot {
+  int32_t w = 0, h = 0;
+  int64_t host_off = -1;  // staging (tightly packed rows)
+  int64_t dev_off = -1;   // device copy
+  int64_t bytes = 0;
+};
+
+struct Request {
+  uint64_t ticket = 0, tag = 0;
+  int n = 0;
+  PlaneSlot p[3];
+  int sel = SEL_ZZ, mode = RDCT_SEL_ZIGZAG, r = 64, shift = 0;
+  uint16_t q[64];
+  double t_submit = 0, t_launch = 0;
+};
+
+struct Batch {
+  std::vector<Request> reqs;
+  int stream = 0;
+  hipEvent_t done = nullptr;
+  int64_t dev_off = -1, dev_bytes = 0;    // descriptors, tables, items, sums
+  int64_t host_off = -1, host_bytes = 0;  // pinned mirror of the same + read-back
+  int64_t o_sse = 0;                      // offset of the error sums in both blocks
+  int n_planes = 0;
+  int64_t n_blocks = 0;
+  double t_launch = 0;
+};
+
+int64_t plane_dev_bytes(int w, int h) { return (int64_t)w * h; }
+
+}  // namespace
+
+struct rdct_server {
+  rdct_server_cfg_t cfg{};
+  int device = 0;
+  int n_cu = 256;
+  uint8_t* dev_base = nullptr;
+  uint8_t* host_base = nullptr;
+  ScaleConsts* d_sc = nullptr;
+  Arena dev, host;
+  hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool stream_busy[4] = {false, false, false, false};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request> pending;
+  std::deque<Batch> inflight;
+  std::deque<rdct_completion_t> done;
+  std::atomic<bool> stop{false};
+  std::thread worker;
+  uint64_t next_ticket = 1;
+  rdct_server_stats_t st{};
+  int64_t inflight_reqs = 0;
+  std::chrono::steady_clock::time_point t0;
+
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+// Device bytes a batch needs for its descriptors, tables, work items and sums.
+int64_t batch_meta_bytes(int n_planes, int n_tables, int64_t n_items) {
+  return (int64_t)sizeof(Plane) * n_planes + (int64_t)sizeof(QuantConsts) * n_tables +
+         (int64_t)sizeof(WorkItem) * n_items + 8 * (int64_t)n_planes + 4 * 256;
+}
+
+int64_t request_items(const Request& r) {
+  int64_t n = 0;
+  for (int i = 0; i < r.n; ++i) n += (rdct_num_blocks(r.p[i].w, r.p[i].h) + 127) / 128;
+  return n;
+}
+
+void complete(rdct_server* s, const Request& r, int status, const uint64_t* sse, double t_done,
+              int batch_planes) {
+  rdct_completion_t c;
+  memset(&c, 0, sizeof(c));
+  c.ticket = r.ticket;
+  c.user_tag = r.tag;
+  c.status = status;
+  c.n_planes = r.n;
+  for (int i = 0; i < r.n; ++i) {
+    c.sse[i] = sse ? sse[i] : 0;
+    c.psnr[i] = sse ? rdct_psnr(sse[i], r.mode, r.p[i].w, r.p[i].h) : 0.0;
+  }
+  c.t_submit_us = r.t_submit;
+  c.t_launch_us = r.t_launch;
+  c.t_done_us = t_done;
+  c.batch_planes = batch_planes;
+  s->done.push_back(c);
+}
+
+void release_request(rdct_server* s, const Request& r) {
+  for (int i = 0; i < r.n; ++i) {
+    if (r.p[i].host_off >= 0) s->host.release(r.p[i].host_off, r.p[i].bytes);
+    if (r.p[i].dev_off >= 0) s->dev.release(r.p[i].dev_off, r.p[i].bytes);
+  }
+}
+
+// Launch one batch on stream b.stream.  Called with the lock held.
+hipError_t launch(rdct_server* s, Batch& b) {
+  hipStream_t st = s->streams[b.stream];
+  // Distinct quantisation tables of the batch.
+  std::vector<std::vector<uint16_t>> tables;
+  std::vector<int> table_of;
+  for (const Request& r : b.reqs) {
+    int t = 0;
+    if (r.sel == SEL_Q) {
+      std::vector<uint16_t> key(r.q, r.q + 64);
+      auto it = std::find(tables.begin(), tables.end(), key);
+      t = (int)(it - tables.begin());
+      if (it == tables.end()) tables.push_back(key);
+    }
+    table_of.push_back(t);
+  }
+  const int n_tables = std::max<int>(1, (int)tables.size());
+  int64_t n_items = 0;
+  for (const Request& r : b.reqs) n_items += request_items(r);
+  // Layout of the descriptor block (same offsets on host and device).
+  const int64_t o_planes = 0;
+  const int64_t o_tables = s->dev.round(o_planes + (int64_t)sizeof(Plane) * b.n_planes);
+  const int64_t o_items = s->dev.round(o_tables + (int64_t)sizeof(QuantConsts) * n_tables);
+  const int64_t o_sse = s->dev.round(o_items + (int64_t)sizeof(WorkItem) * n_items);
+  b.o_sse = o_sse;
+  uint8_t* hb = s->host_base + b.host_off;
+  uint8_t* db = s->dev_base + b.dev_off;
+  Plane* hp = reinterpret_cast<Plane*>(hb + o_planes);
+  QuantConsts* ht = reinterpret_cast<QuantConsts*>(hb + o_tables);
+  WorkItem* hi = reinterpret_cast<WorkItem*>(hb + o_items);
+  uint64_t* dsse = reinterpret_cast<uint64_t*>(db + o_sse);
+  for (size_t t = 0; t < tables.size(); ++t) fill_quant_consts(tables[t].data(), &ht[t]);
+  if (tables.empty()) memset(ht, 0, sizeof(QuantConsts));
+  int k = 0;
+  int64_t it = 0;
+  for (size_t ri = 0; ri < b.reqs.size(); ++ri) {
+    const Request& r = b.reqs[ri];
+    for (int i = 0; i < r.n; ++i, ++k) {
+      const PlaneSlot& p = r.p[i];
+      hipError_t e = hipMemcpyAsync(s->dev_base + p.dev_off, s->host_base + p.host_off,
+                                    (size_t)p.bytes, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return e;
+      Plane P = make_plane(s->dev_base + p.dev_off, p.w, p.h, p.w);
+      P.sse = dsse + k;
+      P.r = r.r;
+      P.keep = keep_bits(r.r);
+      P.r_count = 1;
+      P.shift = r.shift;
+      P.table = table_of[ri];
+      hp[k] = P;
+      for (int t0 = 0; t0 < P.nblocks; t0 += 128) hi[it++] = WorkItem{k, t0};
+      b.n_blocks += P.nblocks;
+    }
+  }
+  hipError_t e = hipMemcpyAsync(db, hb, (size_t)o_sse, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if ((e = launch_zero_u64(dsse, b.n_planes, st)) != hipSuccess) return e;
+  const int sel = b.reqs[0].sel;
+  const int ev = EV_SPATIAL;
+  const int wpg = 4;
+  const int grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2, (n_items + wpg - 1) / wpg));
+  e = launch_batch(sel, CO_NONE, false, ev, reinterpret_cast<Plane*>(db + o_planes),
+                   reinterpret_cast<QuantConsts*>(db + o_tables), s->d_sc,
+                   reinterpret_cast<WorkItem*>(db + o_items), (int32_t)n_items, grid, wpg, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(hb + o_sse, dsse, 8 * (size_t)b.n_planes, hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipEventRecord(b.done, st);
+}
+
+// Plain path: one plane at a time, synchronously (upload, single-plane launch,
+// read back).  Called without the lock.
+void run_plain(rdct_server* s, Request& r) {
+  hipStream_t st = s->streams[0];
+  uint64_t sse[3] = {0, 0, 0};
+  int status = RDCT_OK;
+  uint64_t* dsse = reinterpret_cast<uint64_t*>(s->dev_base);  // first 256 bytes are reserved
+  for (int i = 0; i < r.n && status == RDCT_OK; ++i) {
+    const PlaneSlot& p = r.p[i];
+    uint8_t* dp = s->dev_base + p.dev_off;
+    if (hipMemcpyAsync(dp, s->host_base + p.host_off, (size_t)p.bytes, hipMemcpyHostToDevice, st) !=
+        hipSuccess) {
+      status = RDCT_ERR_HIP;
+      break;
+    }
+    rdct_select_t sel{};
+    sel.mode = r.mode;
+    sel.r = r.r;
+    sel.quality = 50;
+    sel.level_shift = r.shift;
+    sel.qtable = r.q;
+    if (rdct_compress_eval(dp, p.w, p.h, p.w, &sel, 1, nullptr, RDCT_COEF_I32, nullptr, 0, dsse, st) !=
+            RDCT_OK ||
+        hipMemcpyAsync(&sse[i], dsse, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      status = RDCT_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  const double t = s->now_us();
+  complete(s, r, status, status == RDCT_OK ? sse : nullptr, t, 1);
+  release_request(s, r);
+  s->st.completed++;
+  s->st.planes += r.n;
+  s->st.batches += r.n;
+  s->inflight_reqs--;
+  s->cv_done.notify_all();
+}
+
+void worker_main(rdct_server* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    // Retire finished batches.
+    for (auto bi = s->inflight.begin(); bi != s->inflight.end();) {
+      const hipError_t q = hipEventQuery(bi->done);
+      if (q == hipErrorNotReady) {
+        ++bi;
+        continue;
+      }
+      const double t = s->now_us();
+      const int status = q == hipSuccess ? RDCT_OK : RDCT_ERR_HIP;
+      const uint64_t* sums =
+          status == RDCT_OK
+              ? reinterpret_cast<const uint64_t*>(s->host_base + bi->host_off + bi->o_sse)
+              : nullptr;
+      int k = 0;
+      for (Request& r : bi->reqs) {
+        complete(s, r, status, sums ? sums + k : nullptr, t, bi->n_planes);
+        k += r.n;
+        release_request(s, r);
+        s->inflight_reqs--;
+        s->st.completed++;
+      }
+      s->dev.release(bi->dev_off, bi->dev_bytes);
+      s->host.release(bi->host_off, bi->host_bytes);
+      hipEventDestroy(bi->done);
+      s->stream_busy[bi->stream] = false;
+      bi = s->inflight.erase(bi);
+      s->cv_done.notify_all();
+    }
+    if (s->stop && s->inflight.empty()) break;
+
+    bool launched = false;
+    if (!s->stop && !s->pending.empty()) {
+      if (s->cfg.plain) {
+        Request r = s->pending.front();
+        s->pending.pop_front();
+        // Device copy of the planes.
+        bool ok = true;
+        for (int i = 0; i < r.n && ok; ++i) {
+          r.p[i].dev_off = s->dev.alloc(r.p[i].bytes);
+          ok = r.p[i].dev_off >= 0;
+        }
+        if (!ok) {  // cannot happen for a lone request (checked at submit); be safe
+          release_request(s, r);
+          complete(s, r, RDCT_ERR_BUDGET, nullptr, s->now_us(), 0);
+          s->st.completed++;
+          s->cv_done.notify_all();
+          continue;
+        }
+        r.t_launch = s->now_us();
+        s->inflight_reqs++;
+        lk.unlock();
+        run_plain(s, r);
+        lk.lock();
+        continue;
+      }
+      int free_stream = -1;
+      for (int i = 0; i < s->cfg.n_streams; ++i)
+        if (!s->stream_busy[i]) {
+          free_stream = i;
+          break;
+        }
+      if (free_stream >= 0) {
+        Batch b;
+        b.stream = free_stream;
+        const int sel = s->pending.front().sel;
+        int64_t items = 0;
+        while (!s->pending.empty()) {
+          Request& r = s->pending.front();
+          if (r.sel != sel) break;
+          if (b.n_planes + r.n > s->cfg.max_batch_planes) break;
+          if (s->inflight_reqs + (int64_t)b.reqs.size() >= s->cfg.max_inflight) break;
+          bool ok = true;
+          for (int i = 0; i < r.n && ok; ++i) {
+            r.p[i].dev_off = s->dev.alloc(r.p[i].bytes);
+            ok = r.p[i].dev_off >= 0;
+          }
+          if (!ok) {
+            for (int i = 0; i < r.n; ++i)
+              if (r.p[i].dev_off >= 0) {
+                s->dev.release(r.p[i].dev_off, r.p[i].bytes);
+                r.p[i].dev_off = -1;
+              }
+            break;
+          }
+          items += request_items(r);
+          b.n_planes += r.n;
+          b.reqs.push_back(r);
+          s->pending.pop_front();
+        }
+        if (!b.reqs.empty()) {
+          const int64_t meta = batch_meta_bytes(b.n_planes, (int)b.reqs.size(), items);
+          b.dev_off = s->dev.alloc(meta);
+          b.host_off = s->host.alloc(meta);
+          if (b.dev_off < 0 || b.host_off < 0) {
+            // Not enough room for the descriptors: give the requests back.
+            if (b.dev_off >= 0) s->dev.release(b.dev_off, meta);
+            if (b.host_off >= 0) s->host.release(b.host_off, meta);
+            for (auto ri = b.reqs.rbegin(); ri != b.reqs.rend(); ++ri) {
+              for (int i = 0; i < ri->n; ++i) {
+                s->dev.release(ri->p[i].dev_off, ri->p[i].bytes);
+                ri->p[i].dev_off = -1;
+              }
+              s->pending.push_front(*ri);
+            }
+          } else {
+            b.dev_bytes = b.host_bytes = meta;
+            b.t_launch = s->now_us();
+            for (Request& r : b.reqs) r.t_launch = b.t_launch;
+            const hipError_t e = launch(s, b);
+            s->stream_busy[b.stream] = true;
+            s->inflight_reqs += (int64_t)b.reqs.size();
+            s->st.batches++;
+            s->st.planes += b.n_planes;
+            s->st.blocks += b.n_blocks;
+            if (e != hipSuccess && !b.done) {
+              // Nothing was recorded: complete with an error now.
+              for (Request& r : b.reqs) {
+                complete(s, r, RDCT_ERR_HIP, nullptr, s->now_us(), b.n_planes);
+                release_request(s, r);
+                s->inflight_reqs--;
+                s->st.completed++;
+              }
+              s->dev.release(b.dev_off, b.dev_bytes);
+              s->host.release(b.host_off, b.host_bytes);
+              s->stream_busy[b.stream] = false;
+              s->cv_done.notify_all();
+            } else {
+              s->inflight.push_back(std::move(b));
+            }
+            launched = true;
+          }
+        }
+      }
+    }
+    s->st.peak_device_bytes = std::max(s->st.peak_device_bytes, s->dev.in_use());
+    if (launched) continue;
+    if (s->inflight.empty())
+      s->cv_work.wait(lk, [&] { return s->stop.load() || !s->pending.empty(); });
+    else
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+void destroy(rdct_server* s) {
+  if (!s) return;
+  if (s->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+      for (const Request& r : s->pending) release_request(s, r);
+      s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    s->worker.join();
+  }
+  for (int i = 0; i < 4; ++i)
+    if (s->streams[i]) {
+      hipStreamSynchronize(s->streams[i]);
+      hipStreamDestroy(s->streams[i]);
+    }
+  if (s->d_sc) hipFree(s->d_sc);
+  if (s->dev_base) hipFree(s->dev_base);
+  if (s->host_base) hipHostFree(s->host_base);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+rdct_status_t rdct_server_create(const rdct_server_cfg_t* cfg, rdct_server_t** out) {
+  if (!cfg || !out || cfg->budget_bytes < (1 << 20)) return RDCT_ERR_INVALID_ARG;
+  if (cfg->n_streams < 0 || cfg->n_streams > 4 || cfg->max_inflight < 0 || cfg->max_batch_planes < 0 ||
+      cfg->staging_bytes < 0)
+    return RDCT_ERR_INVALID_ARG;
+  *out = nullptr;
+  rdct_server* s = new rdct_server();
+  s->cfg = *cfg;
+  if (!s->cfg.n_streams) s->cfg.n_streams = 2;
+  if (!s->cfg.max_inflight) s->cfg.max_inflight = 4096;
+  if (!s->cfg.max_batch_planes) s->cfg.max_batch_planes = 4096;
+  if (!s->cfg.staging_bytes) s->cfg.staging_bytes = std::min<int64_t>(cfg->budget_bytes / 4, 2ll << 30);
+  s->t0 = std::chrono::steady_clock::now();
+  hipGetDevice(&s->device);
+  s->n_cu = device_cu_count();
+  // The first 256 bytes of the device budget hold the plain path's error sum.
+  if (hipMalloc(&s->dev_base, (size_t)s->cfg.budget_bytes) != hipSuccess ||
+      hipHostMalloc(&s->host_base, (size_t)s->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&s->d_sc, sizeof(ScaleConsts)) != hipSuccess) {
+    destroy(s);
+    return RDCT_ERR_NO_MEMORY;
+  }
+  s->dev.reset(s->cfg.budget_bytes, 256);
+  s->dev.alloc(256);
+  s->host.reset(s->cfg.staging_bytes, 256);
+  if (hipMemcpy(s->d_sc, &scale_consts(), sizeof(ScaleConsts), hipMemcpyHostToDevice) != hipSuccess) {
+    destroy(s);
+    return RDCT_ERR_HIP;
+  }
+  for (int i = 0; i < s->cfg.n_streams; ++i)
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      destroy(s);
+      return RDCT_ERR_HIP;
+    }
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return RDCT_OK;
+}
+
+rdct_status_t rdct_server_submit(rdct_server_t* s, const rdct_request_t* req, uint64_t* ticket) {
+  if (!s || !req || req->n_planes < 1 || req->n_planes > 3) return RDCT_ERR_INVALID_ARG;
+  SelInfo si;
+  rdct_status_t st = check_sel(&req->sel, &si);
+  if (st != RDCT_OK) return st;
+  Request r;
+  r.n = req->n_planes;
+  r.tag = req->user_tag;
+  r.sel = si.sel;
+  r.mode = req->sel.mode == RDCT_SEL_QUANT ? RDCT_SEL_QUANT : RDCT_SEL_ZIGZAG;
+  r.r = si.r;
+  r.shift = si.shift;
+  memcpy(r.q, si.q, sizeof(r.q));
+  int64_t dev_need = 0, items = 0, host_need = 0;
+  for (int i = 0; i < r.n; ++i) {
+    if ((st = check_plane(req->planes[i], req->width[i], req->height[i], req->pitch[i],
+                          kMaxEvalBlocks)) != RDCT_OK)
+      return st;
+    r.p[i].w = req->width[i];
+    r.p[i].h = req->height[i];
+    r.p[i].bytes = plane_dev_bytes(r.p[i].w, r.p[i].h);
+    dev_need += s->dev.round(r.p[i].bytes);
+    host_need += s->host.round(r.p[i].bytes);
+    items += (rdct_num_blocks(r.p[i].w, r.p[i].h) + 127) / 128;
+  }
+  dev_need += s->dev.round(batch_meta_bytes(r.n, 1, items)) + 256;
+  if (dev_need > s->cfg.budget_bytes || host_need > s->cfg.staging_bytes) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.rejected++;
+    return RDCT_ERR_BUDGET;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int i = 0; i < r.n; ++i) {
+      r.p[i].host_off = s->host.alloc(r.p[i].bytes);
+      if (r.p[i].host_off < 0) {
+        for (int j = 0; j < i; ++j) s->host.release(r.p[j].host_off, r.p[j].bytes);
+        s->st.rejected++;
+        return RDCT_ERR_BUSY;
+      }
+    }
+  }
+  // Copy into the reserved staging outside the lock (rows packed to width).
+  for (int i = 0; i < r.n; ++i) {
+    uint8_t* dst = s->host_base + r.p[i].host_off;
+    const uint8_t* src = req->planes[i];
+    const int w = r.p[i].w, h = r.p[i].h;
+    if (req->pitch[i] == w) {
+      memcpy(dst, src, (size_t)w * h);
+    } else {
+      for (int y = 0; y < h; ++y) memcpy(dst + (int64_t)y * w, src + (int64_t)y * req->pitch[i], w);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r.ticket = s->next_ticket++;
+    r.t_submit = s->now_us();
+    s->pending.push_back(r);
+    s->st.submitted++;
+  }
+  s->cv_work.notify_one();
+  if (ticket) *ticket = r.ticket;
+  return RDCT_OK;
+}
+
+rdct_status_t rdct_server_poll(rdct_server_t* s, rdct_completion_t* out, int32_t max, int32_t* n,
+                               int32_t wait_us) {
+  if (!s || !n || max < 0 || (max > 0 && !out)) return RDCT_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [&] { return !s->done.empty(); });
+  int k = 0;
+  while (k < max && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n = k;
+  return RDCT_OK;
+}
+
+rdct_status_t rdct_server_cancel(rdct_server_t* s, uint64_t ticket) {
+  if (!s) return RDCT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+    if (it->ticket == ticket) {
+      complete(s, *it, RDCT_ERR_CANCELLED, nullptr, s->now_us(), 0);
+      release_request(s, *it);
+      s->pending.erase(it);
+      s->st.cancelled++;
+      s->st.completed++;
+      s->cv_done.notify_all();
+      return RDCT_OK;
+    }
+  }
+  return ticket > 0 && ticket < s->next_ticket ? RDCT_ERR_BUSY : RDCT_ERR_NOT_FOUND;
+}
+
+rdct_status_t rdct_server_drain(rdct_server_t* s, int32_t timeout_ms) {
+  if (!s) return RDCT_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                      [&] { return s->st.completed == s->st.submitted; });
+  return ok ? RDCT_OK : RDCT_ERR_BUSY;
+}
+
+rdct_status_t rdct_server_stats(rdct_server_t* s, rdct_server_stats_t* out) {
+  if (!s || !out) return RDCT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  out->device_bytes_in_use = s->dev.in_use();
+  out->pending = (int32_t)s->pending.size();
+  out->inflight = (int32_t)s->inflight_reqs;
+  return RDCT_OK;
+}
+
+void rdct_server_destroy(rdct_server_t* s) { destroy(s); }
+
+}  // extern "C"
