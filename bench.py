@@ -9,6 +9,7 @@ are already resident in device memory, bracketed by device synchronisations.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,22 +28,67 @@ CLOCK_GHZ = 2.4
 ALU_PEAK_TOPS = N_CU * 64 * CLOCK_GHZ / 1000.0
 
 
+# Sources whose change invalidates a stored HBM-traffic record (the kernels,
+# their launch code and the build flags).
+KERNEL_SOURCES = ("paper_1402_6034_amd/csrc/rdct_kernels.hip",
+                  "paper_1402_6034_amd/csrc/rdct_internal.h",
+                  "paper_1402_6034_amd/csrc/rdct_tables.h",
+                  "paper_1402_6034_amd/csrc/rdct_api.cpp",
+                  "paper_1402_6034_amd/csrc/rdct_batch.cpp",
+                  "paper_1402_6034_amd/build.py")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record(workload):
+    """HBM bytes per launch of the workload's dominant kernel, from the counter
+    record profiles/<workload>_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled by
+    a device copy of known size).  None when there is no record or it was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return {"bytes": int(rec["traffic_bytes_per_launch"]),
+                "read": int(rec["read_bytes_per_launch"]),
+                "write": int(rec["write_bytes_per_launch"])}
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
 def event_time_ms(fn, reps):
-    """Average duration of fn() (one launch) from HIP events on torch's current
-    stream, which is the stream every library call here is issued on."""
+    """Average duration of one launch fn(i): HIP events on torch's current stream
+    (the stream every library call here is issued on) bracket `reps` launches
+    issued back to back, so per-launch event overhead does not count."""
     import torch
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    for i in range(reps):
-        starts[i].record()
-        fn(i)
-        ends[i].record()
+    fn(0)
     torch.cuda.synchronize()
-    return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / reps
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(reps):
+        fn(i)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / reps
 
 
 # ---------------------------------------------------------------------------
@@ -54,6 +100,7 @@ class FrameQuant:
     int16 (HBM-bound streaming case).  Six buffer sets (1.2 GB) rotate so the
     256 MB last-level cache never holds the next launch's data."""
     name = "frame-8192-q50-fwd"
+    workload_key = "frame"
     sets = 6
 
     def __init__(self, size=8192):
@@ -112,6 +159,7 @@ class PlainSweep:
     """256 planes of 512 x 512, seeds 0..255: forward, S-scaled retention swept
     over r = 1..45, inverse error and per-plane PSNR; one launch per plane."""
     name = "plain-256x512x512-sweep-r1-45"
+    workload_key = "sweep"
 
     def __init__(self, n=256, size=512):
         import torch
@@ -169,6 +217,7 @@ class RaggedBatch:
     work list (hipGraph replay, autotuned geometry); int16 coefficients and the
     float32 reconstruction are written to HBM."""
     name = "ragged-1000-logU64-4096-q10-90"
+    workload_key = "ragged"
 
     def __init__(self, n=1000, planes_cache=None, autotune=True):
         import numpy as np
@@ -381,9 +430,15 @@ def main():
     nb = wl.blocks_per_step if not isinstance(wl, PlainSweep) else wl.nb1
     alg_bytes = nb * wl.bytes_per_block
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    tr = traffic_record(wl.workload_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel_ms": round(k_ms, 5), "bytes_per_launch": alg_bytes}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["bytes"] if tr else None,
+                "kernel_ms": round(k_ms, 5), "bytes_per_launch": alg_bytes,
+                "kernel_source_sha256": kernel_source_hash()}
+    if tr:
+        roofline["traffic_read"] = tr["read"]
+        roofline["traffic_write"] = tr["write"]
 
     cpu = None
     if args.cpu_budget > 0:

@@ -16,3 +16,4 @@ the text and its image set is not available).
 from .rdct import *  # noqa: F401,F403
 from .image import *  # noqa: F401,F403
 from .spectral import *  # noqa: F401,F403
+from .quality import *  # noqa: F401,F403

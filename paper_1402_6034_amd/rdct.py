@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RDCT_LIB") or os.path.join(_HERE, "librdct.so")
 
 # rdct_status_t
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_MEMORY, ERR_BUDGET, ERR_NOT_FOUND, ERR_BUSY = range(8)
+(OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_MEMORY, ERR_BUDGET, ERR_NOT_FOUND, ERR_BUSY,
+ ERR_CANCELLED) = range(9)
 # rdct_coef_t
 COEF_I32, COEF_I16, COEF_F32 = 0, 1, 2
 # rdct_sel_mode_t

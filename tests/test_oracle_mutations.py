@@ -86,3 +86,58 @@ def test_reconstruction_without_transpose_is_caught(monkeypatch):
         return np.matmul(np.matmul(t, np.asarray(z, dtype=np.float64)), t.T)
     monkeypatch.setattr(O, "inverse_orth", bad)
     _fails(P.test_perfect_reconstruction_with_all_coefficients)
+
+
+# --- comparison transforms and UQI ---------------------------------------------------
+
+import oracle.quality as Q  # noqa: E402
+import test_oracle_quality_pins as QP  # noqa: E402
+
+
+def test_uqi_with_mismatched_normalisation_is_caught(monkeypatch):
+    good = Q.uqi_map
+
+    def bad(x, y, win=8):
+        # variances over n, covariance over n - 1
+        return good(x, y, win) * (win * win) / (win * win - 1)
+    monkeypatch.setattr(O, "uqi_map", bad)
+    _fails(QP.test_uqi_identical_is_one_and_window_count)
+
+
+def test_uqi_mean_factor_typo_is_caught(monkeypatch):
+    def bad(x, y, win=8):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        xw = np.lib.stride_tricks.sliding_window_view(x, (win, win))
+        yw = np.lib.stride_tricks.sliding_window_view(y, (win, win))
+        mx, my = xw.mean(axis=(2, 3)), yw.mean(axis=(2, 3))
+        dx, dy = xw - mx[..., None, None], yw - my[..., None, None]
+        vx, vy = (dx * dx).mean(axis=(2, 3)), (dy * dy).mean(axis=(2, 3))
+        cxy = (dx * dy).mean(axis=(2, 3))
+        return (2 * cxy / (vx + vy)) * (2 * mx * my / (mx * mx + my * mx))
+    monkeypatch.setattr(O, "uqi_map", bad)
+    _fails(QP.test_uqi_shifted_copy_closed_form)
+
+
+def test_missing_transpose_in_inverse_is_caught(monkeypatch):
+    def bad(img, name, r):
+        img = np.asarray(img)
+        h, w = img.shape
+        t, ti = Q.transform(name)
+        a = O.tile(img).astype(np.float64)
+        y = np.matmul(np.matmul(t, a), t.T) * O.retention_mask(r)
+        return O.untile(np.matmul(np.matmul(ti, y), ti), h, w)
+    monkeypatch.setattr(O, "retention_recon", bad)
+    _fails(lambda: QP.test_all_coefficients_reconstruct_exactly("sdct"))
+
+
+def test_transposed_retention_mask_is_caught(monkeypatch):
+    def bad(img, name, r):
+        img = np.asarray(img)
+        h, w = img.shape
+        t, ti = Q.transform(name)
+        a = O.tile(img).astype(np.float64)
+        y = np.matmul(np.matmul(t, a), t.T) * O.retention_mask(r).T
+        return O.untile(np.matmul(np.matmul(ti, y), ti.T), h, w)
+    monkeypatch.setattr(Q, "retention_recon", bad)
+    _fails(QP.test_dct_sse_is_parseval_of_dropped_coefficients)

@@ -1,0 +1,199 @@
+"""Pins of the comparison-transform and quality-metric oracle (CPU only).
+
+Each pin checks the oracle against something other than itself: a library
+routine the definition reduces to (scipy's orthonormal DCT, the polar
+decomposition), closed forms of the UQI, exact rational arithmetic, Parseval's
+identity, or a second exact route through integers.
+"""
+import numpy as np
+import pytest
+import scipy.fft
+from scipy.linalg import polar
+
+import oracle as O
+from paper_1402_6034_amd import synth
+
+
+def _img(seed, h=40, w=48):
+    return synth.render_np(seed, h, w)
+
+
+# --- transforms ---------------------------------------------------------------
+
+def test_dct_is_scipys_orthonormal_dct():
+    t, ti = O.transform("dct")
+    ref = scipy.fft.dct(np.eye(8), type=2, norm="ortho", axis=0)
+    assert np.allclose(t, ref, atol=1e-15)
+    assert np.allclose(ti @ t, np.eye(8), atol=1e-14)
+
+
+def test_rdct_is_the_polar_factor_of_c0():
+    # Section 2: C_orth is the orthogonal factor of C0's polar decomposition.
+    t, ti = O.transform("rdct")
+    u, _ = polar(O.round_off_matrix().astype(np.float64), side="left")
+    assert np.allclose(t, u, atol=1e-14)
+    assert np.allclose(ti, t.T)
+
+
+def test_ceil_variant_is_the_polar_factor_and_not_diagonal():
+    c0 = O.round_variant_matrix("ceil")
+    assert set(np.unique(c0)) <= {0, 1}
+    g = c0 @ c0.T
+    assert np.count_nonzero(g - np.diag(np.diag(g))) > 0     # S is a full matrix
+    t, ti = O.transform("rdct_ceil")
+    u, _ = polar(c0.astype(np.float64), side="left")
+    assert np.allclose(t, u, atol=1e-13)
+    assert np.allclose(t @ t.T, np.eye(8), atol=1e-13)
+
+
+def test_floor_variant_is_degenerate():
+    c0 = O.round_variant_matrix("floor")
+    assert np.all(c0[0] == 0)                 # 2 C[0, n] = 0.707..., floor -> 0
+    assert round(np.linalg.det(c0.astype(np.float64))) == 0
+    with pytest.raises(ValueError):
+        O.transform("rdct_floor")
+
+
+def test_round_variant_is_the_printed_c0():
+    assert np.array_equal(O.round_variant_matrix("round"), O.round_off_matrix())
+
+
+def test_sdct_inverse_is_integer_over_sqrt8():
+    t, ti = O.transform("sdct")
+    assert np.allclose(t * np.sqrt(8.0), np.sign(O.dct_matrix()))
+    m = O.sdct_integer_inverse()
+    assert np.allclose(ti, m / np.sqrt(8.0), atol=1e-14)
+    assert np.max(np.abs(m)) == 2
+    assert not np.allclose(t @ t.T, np.eye(8))                # not orthogonal
+
+
+# --- keep-r reconstruction ------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["dct", "rdct", "sdct", "rdct_ceil"])
+def test_all_coefficients_reconstruct_exactly(name):
+    img = _img(1)
+    rec = O.retention_recon(img, name, 64)
+    assert np.max(np.abs(rec - img)) < 1e-9
+
+
+def test_dct_sse_is_parseval_of_dropped_coefficients():
+    # scipy's dctn per block gives Y; the orthonormal DCT preserves energy, so
+    # the keep-r error is the energy of the dropped zig-zag positions.
+    img = _img(2)
+    h, w = img.shape
+    blocks = img.reshape(h // 8, 8, w // 8, 8).transpose(0, 2, 1, 3).astype(np.float64)
+    y = scipy.fft.dctn(blocks, type=2, norm="ortho", axes=(2, 3))
+    rank = O.zigzag_rank()
+    for r in (1, 3, 10, 27, 45, 63):
+        dropped = float(np.sum((y * y)[..., rank >= r]))
+        sse = O.quality_eval(img, "dct", [r])["sse"][r]
+        assert abs(sse - dropped) <= 1e-9 * max(1.0, dropped)
+
+
+def test_rdct_float_route_equals_exact_integer_route():
+    img = _img(3, 32, 56)
+    ex = O.retention_eval(img, [1, 6, 22, 45])
+    q = O.quality_eval(img, "rdct", [1, 6, 22, 45])
+    for r in (1, 6, 22, 45):
+        assert abs(q["sse"][r] - ex["sse_num"][r] / 576.0 ** 2) <= 1e-9 * ex["sse"][r]
+
+
+def test_sdct_float_route_equals_exact_integer_route():
+    img = _img(4)
+    for r in (1, 5, 17, 45):
+        rec = O.retention_recon(img, "sdct", r)
+        num = O.sdct_numerators(img, r)
+        assert np.max(np.abs(rec - num / 64.0)) < 1e-10
+
+
+def test_dc_only_reconstruction_is_block_mean_for_dct_and_rdct():
+    img = _img(5)
+    h, w = img.shape
+    means = img.reshape(h // 8, 8, w // 8, 8).mean(axis=(1, 3))
+    for name in ("dct", "rdct"):
+        rec = O.retention_recon(img, name, 1)
+        assert np.allclose(rec, np.kron(means, np.ones((8, 8))), atol=1e-10)
+
+
+# --- UQI --------------------------------------------------------------------------
+
+def test_uqi_identical_is_one_and_window_count():
+    x = _img(6, 24, 31).astype(np.float64)
+    m = O.uqi_map(x, x)
+    assert m.shape == (24 - 7, 31 - 7)
+    assert np.allclose(m, 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("a", [0.5, 1.0, 1.7, 3.0])
+def test_uqi_scaled_copy_closed_form(a):
+    # y = a x: s_xy = a s_x^2, s_y^2 = a^2 s_x^2, ybar = a xbar -> Q = (2a / (1 + a^2))^2.
+    x = _img(7, 20, 20).astype(np.float64)
+    assert np.allclose(O.uqi_map(x, a * x), (2 * a / (1 + a * a)) ** 2, atol=1e-13)
+
+
+def test_uqi_shifted_copy_closed_form():
+    # y = x + c: the structure factor is 1, the mean factor 2 m (m + c) / (m^2 + (m + c)^2).
+    x = _img(8, 16, 19).astype(np.float64)
+    c = 13.0
+    mean = np.lib.stride_tricks.sliding_window_view(x, (8, 8)).mean(axis=(2, 3))
+    want = 2 * mean * (mean + c) / (mean ** 2 + (mean + c) ** 2)
+    assert np.allclose(O.uqi_map(x, x + c), want, atol=1e-13)
+
+
+def test_uqi_reflected_window_is_minus_one():
+    x = _img(9, 8, 8).astype(np.float64)
+    y = 2 * x.mean() - x
+    assert O.uqi_map(x, y).shape == (1, 1)
+    assert abs(O.uqi_map(x, y)[0, 0] + 1.0) < 1e-13
+
+
+def test_uqi_flat_windows():
+    x = np.full((8, 8), 100.0)
+    assert O.uqi_map(x, np.full((8, 8), 50.0))[0, 0] == pytest.approx(2 * 100 * 50 / (100 ** 2 + 50 ** 2))
+    assert O.uqi_map(x, x)[0, 0] == 1.0
+    z = np.zeros((8, 8))
+    assert O.uqi_map(z, z)[0, 0] == 1.0
+    # One flat window against a varying one: structure factor 0.
+    v = _img(10, 8, 8).astype(np.float64)
+    assert O.uqi_map(x, v)[0, 0] == 0.0
+
+
+def test_uqi_matches_exact_rationals():
+    rng = np.random.default_rng(11)
+    x = rng.integers(0, 256, size=(10, 11))
+    y = x + rng.integers(-30, 31, size=x.shape)
+    m = O.uqi_map(x, y)
+    for i in range(m.shape[0]):
+        for j in range(m.shape[1]):
+            q = O.uqi_window_exact(x[i:i + 8, j:j + 8], y[i:i + 8, j:j + 8])
+            assert abs(m[i, j] - float(q)) < 1e-12
+
+
+def test_uqi_symmetric_and_bounded():
+    x = _img(12, 30, 30).astype(np.float64)
+    y = O.retention_recon(x.astype(np.uint8), "rdct", 6)
+    m1, m2 = O.uqi_map(x, y), O.uqi_map(y, x)
+    assert np.allclose(m1, m2, atol=1e-15)
+    assert np.all(np.abs(m1) <= 1 + 1e-12)
+
+
+# --- the comparison of Section 3 -----------------------------------------------------
+
+def test_ape_values():
+    assert O.ape(1.1, 1.0) == pytest.approx(10.0)
+    assert O.ape(0.9, 1.0) == pytest.approx(10.0)
+    assert O.ape(2.0, 2.0) == 0.0
+
+
+def test_metrics_improve_with_r_and_dct_beats_approximations_on_mse():
+    img = _img(13, 64, 64)
+    rs = [1, 5, 10, 20, 45]
+    res = {n: O.quality_eval(img, n, rs) for n in ("dct", "rdct", "sdct")}
+    for n, q in res.items():
+        mses = [q["mse"][r] for r in rs]
+        assert all(a >= b for a, b in zip(mses, mses[1:])), n
+    for r in rs[1:]:
+        # The exact DCT compacts energy best among orthogonal transforms.
+        assert res["dct"]["mse"][r] <= res["rdct"]["mse"][r] + 1e-9
+    # r = 1 keeps DC only; DCT and C_orth share the DC row (Section 2).
+    assert res["dct"]["mse"][1] == pytest.approx(res["rdct"]["mse"][1], rel=1e-12)
