@@ -33,10 +33,6 @@ void fill_quant_consts(const uint16_t q[64], QuantConsts* out) {
   }
 }
 
-void fill_scale_consts(ScaleConsts* out) {
-  for (int kl = 0; kl < 64; ++kl) out->ss[kl] = scale_kl(kl >> 3, kl & 7);
-}
-
 uint64_t keep_bits(int r) {
   uint64_t m = 0;
   for (int kl = 0; kl < 64; ++kl)
@@ -61,15 +57,6 @@ int device_cu_count() {
 }
 
 int default_waves_per_wg() { return g_waves_per_wg.load(); }
-
-const ScaleConsts& scale_consts() {
-  static const ScaleConsts sc = [] {
-    ScaleConsts s;
-    fill_scale_consts(&s);
-    return s;
-  }();
-  return sc;
-}
 
 rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out) {
   if (!s) return RDCT_ERR_INVALID_ARG;
@@ -166,7 +153,7 @@ rdct_status_t rdct_forward(const uint8_t* src, int32_t width, int32_t height, in
   P.keep = keep_bits(si.r);
   P.r_count = 1;
   P.shift = si.shift;
-  return hip_status(launch_plane(si.sel, co, false, EV_NONE, P, si.qc, scale_consts(),
+  return hip_status(launch_plane(si.sel, co, false, EV_NONE, P, si.qc,
                                  default_waves_per_wg(), (hipStream_t)stream));
 }
 
@@ -190,7 +177,7 @@ rdct_status_t rdct_inverse(const void* coef, rdct_coef_t coef_type, int32_t widt
     else return RDCT_ERR_INVALID_ARG;
   }
   return hip_status(launch_inverse(kind, coef, width, height, si.r, si.shift, dst, dst_pitch,
-                                   si.qc, scale_consts(), (hipStream_t)stream));
+                                   si.qc, (hipStream_t)stream));
 }
 
 rdct_status_t rdct_compress_eval(const uint8_t* src, int32_t width, int32_t height,
@@ -232,7 +219,7 @@ rdct_status_t rdct_compress_eval(const uint8_t* src, int32_t width, int32_t heig
   P.shift = si.shift;
   hipError_t e = launch_zero_u64(sse_out, r_count, (hipStream_t)stream);
   if (e != hipSuccess) return RDCT_ERR_HIP;
-  return hip_status(launch_plane(si.sel, co, recon_out != nullptr, ev, P, si.qc, scale_consts(),
+  return hip_status(launch_plane(si.sel, co, recon_out != nullptr, ev, P, si.qc,
                                  default_waves_per_wg(), (hipStream_t)stream));
 }
 

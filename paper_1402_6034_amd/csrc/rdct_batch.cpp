@@ -30,7 +30,6 @@ struct rdct_batch_plan {
   uint64_t* sse = nullptr;
   Plane* d_planes = nullptr;
   QuantConsts* d_tables = nullptr;
-  ScaleConsts* d_sc = nullptr;
   WorkItem* d_items = nullptr;
   rdct_tuning_t tuning{};
   int device = 0;
@@ -54,7 +53,6 @@ void free_plan(rdct_batch_plan* p) {
   }
   if (p->d_planes) hipFree(p->d_planes);
   if (p->d_tables) hipFree(p->d_tables);
-  if (p->d_sc) hipFree(p->d_sc);
   if (p->d_items) hipFree(p->d_items);
   delete p;
 }
@@ -68,7 +66,7 @@ int grid_of(const rdct_batch_plan* p, const rdct_tuning_t& t) {
 hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t s) {
   hipError_t e = launch_zero_u64(p->sse, p->n_planes, s);
   if (e != hipSuccess) return e;
-  return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables, p->d_sc,
+  return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables,
                       p->d_items, p->n_items, grid_of(p, t), t.waves_per_wg, s);
 }
 
@@ -196,7 +194,6 @@ rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
 
   bool ok = hipMalloc(&p->d_planes, sizeof(Plane) * n) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(QuantConsts) * tables.size()) == hipSuccess &&
-            hipMalloc(&p->d_sc, sizeof(ScaleConsts)) == hipSuccess &&
             hipMalloc(&p->d_items, sizeof(WorkItem) * items.size()) == hipSuccess;
   if (!ok) {
     free_plan(p);
@@ -205,8 +202,6 @@ rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
   ok = hipMemcpy(p->d_planes, hp.data(), sizeof(Plane) * n, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, tables.data(), sizeof(QuantConsts) * tables.size(),
                  hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_sc, &scale_consts(), sizeof(ScaleConsts), hipMemcpyHostToDevice) ==
-           hipSuccess &&
        hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(),
                  hipMemcpyHostToDevice) == hipSuccess &&
        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) == hipSuccess;

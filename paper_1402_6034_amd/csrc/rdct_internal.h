@@ -39,11 +39,6 @@ struct QuantConsts {
   int32_t qi[64];
 };
 
-// Scale factors s_k s_l = 1 / sqrt(g_k g_l) in float64.
-struct ScaleConsts {
-  double ss[64];
-};
-
 enum SelKind { SEL_ZZ = 0, SEL_Q = 1 };
 enum CoefKind { CO_NONE = 0, CO_I32 = 1, CO_I16 = 2, CO_F32 = 3 };
 // EV_SPATIAL: squared error from the reconstruction, pixel by pixel.
@@ -68,21 +63,20 @@ struct Geometry {
 };
 
 void fill_quant_consts(const uint16_t q[64], QuantConsts* out);
-void fill_scale_consts(ScaleConsts* out);
 uint64_t keep_bits(int r);
 
 hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
-                        const QuantConsts& qc, const ScaleConsts& sc, int waves_per_wg,
+                        const QuantConsts& qc, int waves_per_wg,
                         hipStream_t stream);
 hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height,
                           int32_t r, int32_t shift, float* dst, int64_t dpitch,
-                          const QuantConsts& qc, const ScaleConsts& sc, hipStream_t stream);
+                          const QuantConsts& qc, hipStream_t stream);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t stream);
 
 // Persistent batch launch over a work list.  `planes` and `tables` are device
 // arrays; `items` has n_items entries.
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
-                        const QuantConsts* tables, const ScaleConsts* sc_dev,
+                        const QuantConsts* tables,
                         const WorkItem* items, int32_t n_items, int32_t grid,
                         int32_t waves_per_wg, hipStream_t stream);
 
@@ -105,7 +99,6 @@ rdct_status_t check_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitc
                           int64_t max_blocks);
 Plane make_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch);
 bool aligned(const void* p, uintptr_t a);
-const ScaleConsts& scale_consts();
 
 
 }  // namespace rdct

@@ -32,6 +32,32 @@ template <typename T>
 __device__ __forceinline__ RDCT_GLOBAL T* gptr(T* p) {
   return (RDCT_GLOBAL T*)p;
 }
+// Quantisation tables are read through constant-address-space pointers, which
+// become scalar loads.
+#define RDCT_CONST __attribute__((address_space(4)))
+typedef const RDCT_CONST QuantConsts* QCPtr;
+
+// Returns p once `dep` has been computed.  A table is 192 dwords, more than the
+// scalar register file: without this the compiler loads all of it up front and
+// spills it.  Gating the pointer of row K + 2 on a result of row K keeps one row
+// of look-ahead.
+__device__ __forceinline__ QCPtr qc_after(QCPtr p, uint32_t dep) {
+  asm volatile("" : "+s"(p) : "v"(dep));
+  return p;
+}
+__device__ __forceinline__ QCPtr qc_after_s(QCPtr p, int dep) {
+  asm volatile("" : "+s"(p) : "s"(dep));
+  return p;
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -234,7 +260,7 @@ __device__ __forceinline__ void store_i16(int16_t* out, const s16x2 (&v)[8][8], 
 }
 
 __device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], uint64_t keep,
-                                          const ScaleConsts& sc, int h) {
+                                          int h) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     float e[8];
@@ -245,14 +271,6 @@ __device__ __forceinline__ void store_f32(float* out, const s16x2 (&v)[8][8], ui
     reinterpret_cast<float4*>(out)[2 * k] = make_float4(e[0], e[1], e[2], e[3]);
     reinterpret_cast<float4*>(out)[2 * k + 1] = make_float4(e[4], e[5], e[6], e[7]);
   }
-}
-
-// Store one reconstructed row of 8 pixels of a block that lies inside the plane,
-// on a plane whose rows are 16-byte aligned (checked on the host).
-__device__ __forceinline__ void store_row_full(const Plane& P, int x0, int y, const float (&px)[8]) {
-  RDCT_GLOBAL float* row = gptr(P.recon) + (int64_t)y * P.rpitch + x0;
-  reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[0] = (f32x4){px[0], px[1], px[2], px[3]};
-  reinterpret_cast<RDCT_GLOBAL f32x4*>(row)[1] = (f32x4){px[4], px[5], px[6], px[7]};
 }
 
 // Store one reconstructed row of 8 pixels (clipped to the plane).
@@ -350,28 +368,63 @@ __device__ __forceinline__ uint64_t retention_inverse(const Plane& P, const s16x
   return (uint64_t)acc;  // exact: < 2^53 per block
 }
 
-// Quantise row K of block h of the pair: store the row into the lane's stage,
-// (ERR) accumulate the coefficient-domain error, and write q back over half h of
-// the pair (the inverse reads it from there).
-template <int K, int CO, bool ERR, int... L>
-__device__ __forceinline__ void quant_row(s16x2 (&row)[8], int h, const QuantConsts& qc,
-                                          const ScaleConsts& sc, uint8_t* stage, double& err,
-                                          std::integer_sequence<int, L...>) {
+// ---------------------------------------------------------------------------
+// Quantisation path.  Both blocks of a lane's pair are quantised together, so
+// every table constant is read once per chunk; q of the high block waits in
+// registers (16-bit pairs) while the low block's stage is written out.
+// ---------------------------------------------------------------------------
+// Per-block error of the quantisation path in the coefficient domain,
+// ||Z - q Q||^2 (the orthogonal C_orth preserves it, Section 2).  At rational
+// positions (s_k s_l = 1/c, c = g_k) Z - qQ = (Y - c qQ) / c exactly, so the
+// squares are summed in integers per c; irrational positions use float64.
+struct QErr {
+  double irr = 0.0;
+  int r8 = 0, r6 = 0, r4 = 0;
+};
+
+__device__ __forceinline__ uint64_t qerr_units(const QErr& e) {
+  // |Y - c qQ| <= c Q / 2 + 1, so each sum stays far below 2^31.
+  const double rat = (double)e.r8 * (1.0 / 64.0) + (double)e.r6 / 36.0 + (double)e.r4 * (1.0 / 16.0);
+  return (uint64_t)__builtin_fma(e.irr + rat, 1048576.0, 0.5);
+}
+
+// Quantise one coefficient y at position KL; z = q Q (|z| < 2^15) for the inverse.
+template <int KL, bool ERR>
+__device__ __forceinline__ int quant_one(int y, uint64_t qm, int Q, QErr& e, int& z) {
+  constexpr int k = KL >> 3, l = KL & 7;
+  const int q = quantize<KL>(y, qm);
+  z = __mul24(q, Q);
+  if constexpr (ERR) {
+    if constexpr (rational_pos(k, l)) {
+      const int en = y - kGram[k] * z;
+      if constexpr (kGram[k] == 8) e.r8 += __mul24(en, en);
+      else if constexpr (kGram[k] == 6) e.r6 += __mul24(en, en);
+      else e.r4 += __mul24(en, en);
+    } else {
+      // z_kl - q Q with z_kl = s_k s_l Y: one rounding (FMA) per coefficient.
+      const double d = __builtin_fma((double)y, scale_kl(k, l), -(double)z);
+      e.irr = __builtin_fma(d, d, e.irr);
+    }
+  }
+  return q;
+}
+
+// Row K of block h of the pair: q goes to the lane's stage; with WB, q Q
+// replaces half h of the row's pairs (|q Q| < 2^15) for the inverse.  Returns a
+// value of the row's result, used to gate the table reads of a later row.
+template <int K, int CO, bool ERR, bool WB, int... L>
+__device__ __forceinline__ uint32_t quant_row(s16x2 (&row)[8], int h, QCPtr qc, uint8_t* stage,
+                                              QErr& e, std::integer_sequence<int, L...>) {
   int q[8];
-  // v_perm selectors that replace half h of a pair by the low half of q.
+  // v_perm_b32 selectors that replace half h of a pair by the low half of z.
   const uint32_t put = h ? 0x01000504u : 0x07060100u;
   auto one = [&](auto lc) {
     constexpr int l = decltype(lc)::value;
     constexpr int kl = K * 8 + l;
-    const int y = half(row[l], h);
-    const int qq = quantize<kl>(y, qc.qm[kl]);
-    q[l] = qq;
-    if constexpr (ERR) {
-      // z - q Q with z = s_k s_l Y: one rounding (FMA) per coefficient.
-      const double d = __builtin_fma((double)y, scale_kl(kl >> 3, kl & 7), -(double)__mul24(qq, qc.qi[kl]));
-      err = __builtin_fma(d, d, err);
-    }
-    row[l] = as_pair(__builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, row[l]), (uint32_t)qq, put));
+    int z;
+    q[l] = quant_one<kl, ERR>(half(row[l], h), qc->qm[kl], qc->qi[kl], e, z);
+    if constexpr (WB)
+      row[l] = as_pair(__builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, row[l]), (uint32_t)z, put));
   };
   (one(std::integral_constant<int, L>{}), ...);
   if constexpr (CO == CO_I32) {
@@ -385,56 +438,149 @@ __device__ __forceinline__ void quant_row(s16x2 (&row)[8], int h, const QuantCon
       d[m] = ((uint32_t)q[2 * m] & 0xffffu) | ((uint32_t)q[2 * m + 1] << 16);
     *reinterpret_cast<uint4*>(stage + K * 16) = make_uint4(d[0], d[1], d[2], d[3]);
   }
+  return (uint32_t)q[7];
 }
 
-template <int CO, bool ERR, int... K>
-__device__ __forceinline__ void quant_rows(s16x2 (&v)[8][8], int h, const QuantConsts& qc,
-                                           const ScaleConsts& sc, uint8_t* stage, double& err,
-                                           std::integer_sequence<int, K...>) {
-  (quant_row<K, CO, ERR>(v[K], h, qc, sc, stage, err, std::make_integer_sequence<int, 8>{}), ...);
+template <int CO, bool ERR, bool WB>
+__device__ __forceinline__ void quant_rows(s16x2 (&v)[8][8], int h, QCPtr qc, uint8_t* stage,
+                                           QErr& e) {
+  QCPtr row_qc[8];
+  row_qc[0] = qc;
+  row_qc[1] = qc;
+  static_for<0, 8>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const uint32_t dep = quant_row<K, CO, ERR, WB>(v[K], h, row_qc[K], stage, e,
+                                                   std::make_integer_sequence<int, 8>{});
+    if constexpr (K + 2 < 8) row_qc[K + 2] = qc_after(qc, dep);
+    // Finish the row (including its error terms) before the next one starts.
+    __builtin_amdgcn_sched_barrier(0);
+  });
 }
 
-// Inverse of the quantisation path for block h: A' = C0^T S (q . Q) S C0 + shift.
-// The column pass (over k) is exact integer arithmetic grouped by the three
-// values of s_k: with Z = q Q, column l gives p = Z0 + Z4 and m = Z0 - Z4
-// (s = 1/sqrt8), Z2 and Z6 (s = 1/2), and the odd combinations b0..b3 of
-// Z1, Z3, Z5, Z7 (s = 1/sqrt6) -- the transposed flow graph without its last
-// stage.  Rows i and 7 - i of C0^T S Z are then a_i +- b_i with
-// a_i = {p or m}/sqrt8 +- {Z2 or Z6}/2 and b_i = b_i/sqrt6; scaled by s_l they
-// feed the float64 row pass.  Only 64 int32 values and two float64 rows are live.
-template <bool RECON, bool SP, bool FULL>
-__device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8][8], int h,
-                                              const QuantConsts& qc, const ScaleConsts& sc,
-                                              const uint32_t (&a)[16], int x0, int y0,
-                                              double& err) {
-  int cp[8], cm[8], c2[8], c6[8], cb[4][8];
+// Inverse of the quantisation path, A' = C0^T S (q . Q) S C0 + shift.
+// Column pass (over k), exact, on the (low, high) 16-bit pairs of q Q: grouped
+// by the three values of s_k, column l gives p = Z0 + Z4 and m = Z0 - Z4
+// (s = 1/sqrt8), Z2 and Z6 (s = 1/2) and the odd combinations b0..b3 of Z1, Z3,
+// Z5, Z7 (s = 1/sqrt6) -- the transposed flow graph without its last stage.
+// Every partial sum is below 2^15 in magnitude.  The level shift enters as
+// 8 * shift on Z_00 (the DC basis function of C_orth is 1/8 everywhere).
+// Results replace the rows of v: 0 = p, 1 = m, 2 = Z2, 3 = Z6, 4..7 = b0..b3.
+__device__ __forceinline__ void quant_columns_pair(s16x2 (&v)[8][8], int shift) {
+  const short s8 = (short)(8 * shift);
 #pragma unroll
   for (int l = 0; l < 8; ++l) {
-    int z[8];
+    s16x2 z[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = __mul24(half(v[k][l], h), qc.qi[k * 8 + l]);
-    // The level shift: adding 8 * shift to Z_00 adds shift to every pixel (the
-    // DC basis function of C_orth is 1/8 everywhere).
-    if (l == 0) z[0] += 8 * P.shift;
-    cp[l] = z[0] + z[4];
-    cm[l] = z[0] - z[4];
-    c2[l] = z[2];
-    c6[l] = z[6];
-    cb[0][l] = z[1] + (z[3] + z[5]);
-    cb[1][l] = z[1] - (z[5] + z[7]);
-    cb[2][l] = (z[1] + z[7]) - z[3];
-    cb[3][l] = z[5] - (z[3] + z[7]);
+    for (int k = 0; k < 8; ++k) z[k] = v[k][l];
+    if (l == 0) z[0] += (s16x2){s8, s8};
+    v[0][l] = z[0] + z[4];
+    v[1][l] = z[0] - z[4];
+    v[2][l] = z[2];
+    v[3][l] = z[6];
+    v[4][l] = z[1] + (z[3] + z[5]);
+    v[5][l] = z[1] - (z[5] + z[7]);
+    v[6][l] = (z[1] + z[7]) - z[3];
+    v[7][l] = z[5] - (z[3] + z[7]);
   }
+}
+
+// Reconstruction through LDS.  Written straight from the lanes, a row of a
+// block is 32 bytes and lanes are 32 bytes apart, so every 16-byte store
+// instruction leaves gaps that the next one fills; HBM writes that way run far
+// below contiguous ones.  For planes made of whole blocks the row pass instead
+// writes four rows of the 64 blocks of one half into the wave's stage (one
+// padded 2 KB slot per row) and the wave stores each slot as two contiguous
+// 1 KB pieces.
+constexpr int kReconSlot = 64 * 32 + 16;
+constexpr int kReconStageBytes = 4 * kReconSlot;
+
+// LDS bytes of a wave's stage: the coefficient stage, or the reconstruction
+// staging of whole-block quantisation planes if that is larger.
+template <int SEL, int CO, bool RECON, int EV>
+constexpr int wave_stage_bytes() {
+  constexpr int coef = Stage<CO>::wave_bytes;
+  return (SEL == SEL_Q && RECON && EV == EV_COEF && kReconStageBytes > coef) ? kReconStageBytes
+                                                                              : coef;
+}
+
+__device__ __forceinline__ void recon_stage_row(uint8_t* stage_wave, int slot, int lane,
+                                                const float (&px)[8]) {
+  f32x4* p = reinterpret_cast<f32x4*>(stage_wave + slot * kReconSlot + lane * 32);
+  p[0] = (f32x4){px[0], px[1], px[2], px[3]};
+  p[1] = (f32x4){px[4], px[5], px[6], px[7]};
+}
+
+// Where the lanes store: lane j writes piece (j & 1) of blocks j / 2 and
+// 32 + j / 2 of the half.
+struct ReconFlush {
+  int64_t off0, off1;  // float offsets of those pieces' row 0 in the plane
+  bool ok0, ok1;       // block inside the plane (the last chunk may be short)
+};
+
+__device__ __forceinline__ ReconFlush recon_flush_setup(const Plane& P, int x0, int y0,
+                                                        int nvalid, int lane) {
+  const int b0 = lane >> 1, b1 = 32 + (lane >> 1);
+  const int piece = (lane & 1) * 4;
+  ReconFlush f;
+  const int xa = __shfl(x0, b0, 64), ya = __shfl(y0, b0, 64);
+  const int xb = __shfl(x0, b1, 64), yb = __shfl(y0, b1, 64);
+  f.off0 = (int64_t)ya * P.rpitch + xa + piece;
+  f.off1 = (int64_t)yb * P.rpitch + xb + piece;
+  f.ok0 = b0 < nvalid;
+  f.ok1 = b1 < nvalid;
+  return f;
+}
+
+__device__ __forceinline__ void recon_flush_rows(const Plane& P, const uint8_t* stage_wave,
+                                                 const ReconFlush& f, const int (&rows)[4],
+                                                 int lane) {
+  RDCT_GLOBAL float* out = gptr(P.recon);
+  // Rows are 16-byte aligned unless the caller's pointer or pitch is not.
+  const bool al16 = ((reinterpret_cast<uintptr_t>(P.recon) & 15u) | (P.rpitch & 3)) == 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const uint8_t* slot = stage_wave + s * kReconSlot;
+    const int64_t ro = (int64_t)rows[s] * P.rpitch;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (m ? f.ok1 : f.ok0) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(slot + 1024 * m + lane * 16);
+        RDCT_GLOBAL float* dst = out + (m ? f.off1 : f.off0) + ro;
+        if (al16) {
+          __builtin_nontemporal_store(v, reinterpret_cast<RDCT_GLOBAL f32x4*>(dst));
+        } else {
+          dst[0] = v.x;
+          dst[1] = v.y;
+          dst[2] = v.z;
+          dst[3] = v.w;
+        }
+      }
+    }
+  }
+}
+
+// Row pass (over l) in float64 for block h of the pair.  Rows i and 7 - i of
+// C0^T S Z are a_i +- b_i with a_i = {p or m}/sqrt8 +- {Z2 or Z6}/2 and
+// b_i = b_i/sqrt6; scaled by s_l they feed the transposed flow graph.  With SP,
+// accumulates the pixel-domain squared error over the block's own pixels.
+template <bool RECON, bool SP, bool STAGED>
+__device__ __forceinline__ void quant_row_pass(const Plane& P, const s16x2 (&c)[8][8], int h,
+                                               const uint32_t (&a)[16], int x0, int y0,
+                                               double& err, uint8_t* stage_wave, int lane,
+                                               int nvalid) {
+  ReconFlush fl;
+  if constexpr (RECON && STAGED) fl = recon_flush_setup(P, x0, y0, nvalid, lane);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double up[8], um[8];
 #pragma unroll
     for (int l = 0; l < 8; ++l) {
-      const int e8 = (i == 0 || i == 3) ? cp[l] : cm[l];
-      const int e4 = (i == 0 || i == 3) ? c2[l] : c6[l];
+      const int e8 = half(c[(i == 0 || i == 3) ? 0 : 1][l], h);
+      const int e4 = half(c[(i == 0 || i == 3) ? 2 : 3][l], h);
+      const int eb = half(c[4 + i][l], h);
       const double s4 = (i == 0 || i == 2) ? scale_kl(2, l) : -scale_kl(2, l);
       const double al = __builtin_fma((double)e4, s4, (double)e8 * scale_kl(0, l));
-      const double be = (double)cb[i][l] * scale_kl(1, l);
+      const double be = (double)eb * scale_kl(1, l);
       up[l] = al + be;
       um[l] = al - be;
     }
@@ -448,8 +594,8 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
         float px[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) px[j] = (float)o[j];
-        if constexpr (FULL)
-          store_row_full(P, x0, y0 + row, px);
+        if constexpr (STAGED)
+          recon_stage_row(stage_wave, (i & 1) * 2 + side, lane, px);
         else
           store_row(P, x0, y0 + row, px);
       }
@@ -463,25 +609,16 @@ __device__ __forceinline__ void quant_inverse(const Plane& P, const s16x2 (&v)[8
         }
       }
     }
+    if constexpr (RECON && STAGED) {
+      if (i & 1) {
+        // Slots hold rows i - 1, 8 - i, i, 7 - i.
+        const int rows[4] = {i - 1, 8 - i, i, 7 - i};
+        wave_sync();
+        recon_flush_rows(P, stage_wave, fl, rows, lane);
+        wave_sync();
+      }
+    }
   }
-}
-
-// Quantisation path for block h of the pair: q = round(z / Q) exactly, staged for
-// output as it is produced; then the inverse.  Returns round(2^20 * block SSE):
-// from ||Z - q Q||^2 (EV_COEF) or pixel by pixel over the block's own pixels
-// (EV_SPATIAL).
-template <int CO, bool RECON, int EV>
-__device__ __forceinline__ uint64_t quant_block(const Plane& P, s16x2 (&v)[8][8], int h,
-                                                const QuantConsts& qc, const ScaleConsts& sc,
-                                                uint8_t* stage, const uint32_t (&a)[16], int x0,
-                                                int y0) {
-  constexpr bool ERR = (EV == EV_COEF);
-  constexpr bool SP = (EV == EV_SPATIAL);
-  double err = 0.0;
-  quant_rows<CO, ERR>(v, h, qc, sc, stage, err, std::make_integer_sequence<int, 8>{});
-  // EV_COEF is only used for planes made of whole blocks.
-  if constexpr (RECON || SP) quant_inverse<RECON, SP, EV == EV_COEF>(P, v, h, qc, sc, a, x0, y0, err);
-  return (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t s) {
@@ -511,8 +648,7 @@ __device__ __forceinline__ void chunk_load(const Plane& P, int t0, int lane, Pix
 }
 
 template <int SEL, int CO, bool RECON, int EV>
-__device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& qc,
-                                            const ScaleConsts& sc, const Pixels& px, int lane,
+__device__ __forceinline__ void plane_chunk(const Plane& P, QCPtr qc, const Pixels& px, int lane,
                                             uint32_t* lds_wave, uint8_t* stage_wave) {
   const int t0 = px.t0;
   const int tl = t0 + lane, th = t0 + 64 + lane;
@@ -525,24 +661,57 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& q
   forward_pair(al, ah, P.shift, v);
 
   if constexpr (SEL == SEL_Q) {
+    constexpr bool ERR = (EV == EV_COEF);
+    constexpr bool SP = (EV == EV_SPATIAL);
+    constexpr bool WB = RECON || SP;
     uint64_t s = 0;
     uint8_t* my_stage = stage_wave + lane * Stage<CO>::stride;
-    // One block of the pair at a time keeps a single 8x8 inverse live.
+    // Quantise one block of the pair at a time through the lane's stage slot.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      if (h ? vh : vl) {
-        uint32_t a[16];
-        if constexpr (EV == EV_SPATIAL) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
-        }
-        s += quant_block<CO, RECON, EV>(P, v, h, qc, sc, my_stage, a, h ? xh : xl, h ? yh : yl);
+      QErr e;
+      quant_rows<CO, ERR, WB>(v, h, qc_after_s(qc, h), my_stage, e);
+      if constexpr (ERR) {
+        const uint64_t valid = (uint64_t)0 - (uint64_t)(h ? vh : vl);
+        s += qerr_units(e) & valid;
+        // Materialise the sum here: otherwise the compiler sinks the whole error
+        // computation past the stage flush and keeps its inputs live through it.
+        asm volatile("" : "+v"(s));
       }
       if constexpr (CO != CO_NONE) {
         const int first = t0 + 64 * h;
+        // Recompute the flush addresses in every iteration rather than keeping
+        // them live (and spilled) across the loop.
+        int ln = lane;
+        asm volatile("" : "+v"(ln) : "s"(h));
         wave_sync();
-        flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), lane);
+        flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), ln);
         wave_sync();
+      }
+    }
+    if constexpr (WB) {
+      quant_columns_pair(v, P.shift);
+      // One block of the pair at a time keeps a single float64 row pass live.
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        // The staged store is a wave-wide operation: every lane takes part, and
+        // lanes past the end of the plane are masked at the store.
+        if constexpr (!(RECON && EV == EV_COEF)) {
+          if (!(h ? vh : vl)) continue;
+        }
+        uint32_t a[16];
+        if constexpr (SP) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
+        }
+        double err = 0.0;
+        // EV_COEF is only used for planes made of whole blocks; those stage the
+        // reconstruction.
+        const int first = t0 + 64 * h;
+        quant_row_pass<RECON, SP, EV == EV_COEF>(P, v, h, a, h ? xh : xl, h ? yh : yl, err,
+                                                 stage_wave, lane,
+                                                 min(64, max(0, P.nblocks - first)));
+        if constexpr (SP) s += (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
       }
     }
     if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
@@ -563,7 +732,7 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, const QuantConsts& q
         else if constexpr (CO == CO_I16)
           store_i16(reinterpret_cast<int16_t*>(my_stage), v, keep, h);
         else
-          store_f32(reinterpret_cast<float*>(my_stage), v, keep, sc, h);
+          store_f32(reinterpret_cast<float*>(my_stage), v, keep, h);
       }
       const int first = t0 + 64 * h;
       wave_sync();
@@ -640,8 +809,7 @@ struct Prefetch {
 };
 
 template <int SEL, int CO, bool RECON, int EV>
-__device__ __forceinline__ void plane_kernel_body(const Plane& P, const QuantConsts& qc,
-                                                  const ScaleConsts& sc) {
+__device__ __forceinline__ void plane_kernel_body(const Plane& P, QCPtr qc) {
   // One chunk of 128 blocks per wave; the grid covers the plane.
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
@@ -650,20 +818,33 @@ __device__ __forceinline__ void plane_kernel_body(const Plane& P, const QuantCon
   const int c = blockIdx.x * wpg + wave;
   if (c * 128 >= P.nblocks) return;
   uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
-                   wave * Stage<CO>::wave_bytes;
+                   wave * wave_stage_bytes<SEL, CO, RECON, EV>();
   Pixels cur;
   chunk_load(P, c * 128, lane, cur);
-  plane_chunk<SEL, CO, RECON, EV>(P, qc, sc, cur, lane, lds + wave * (64 * 65), stage);
+  plane_chunk<SEL, CO, RECON, EV>(P, qc, cur, lane, lds + wave * (64 * 65), stage);
+}
+
+// The single-plane kernels take the quantisation table by value, so a call needs
+// no device allocation; it is read in place from the kernel-argument segment,
+// whose layout is that of PlaneArgs.
+struct PlaneArgs {
+  Plane P;
+  QuantConsts qc;
+};
+
+__device__ __forceinline__ QCPtr kernarg_table() {
+  const RDCT_CONST char* seg = (const RDCT_CONST char*)__builtin_amdgcn_kernarg_segment_ptr();
+  return (QCPtr)(seg + offsetof(PlaneArgs, qc));
 }
 
 template <int SEL, int CO, bool RECON, int EV>
-__global__ __launch_bounds__(256, 2) void k_plane(Plane P, QuantConsts qc, ScaleConsts sc) {
-  plane_kernel_body<SEL, CO, RECON, EV>(P, qc, sc);
+__global__ __launch_bounds__(256, 2) void k_plane(Plane P, QuantConsts /*qc*/) {
+  plane_kernel_body<SEL, CO, RECON, EV>(P, kernarg_table());
 }
 
 template <int SEL, int CO, bool RECON, int EV>
-__global__ __launch_bounds__(256, 1) void k_plane_w(Plane P, QuantConsts qc, ScaleConsts sc) {
-  plane_kernel_body<SEL, CO, RECON, EV>(P, qc, sc);
+__global__ __launch_bounds__(256, 1) void k_plane_w(Plane P, QuantConsts /*qc*/) {
+  plane_kernel_body<SEL, CO, RECON, EV>(P, kernarg_table());
 }
 
 // Persistent batch kernel: workgroups stride over a device work list; each wave
@@ -672,7 +853,6 @@ __global__ __launch_bounds__(256, 1) void k_plane_w(Plane P, QuantConsts qc, Sca
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
-                                                  const ScaleConsts* __restrict__ scp,
                                                   const WorkItem* __restrict__ items,
                                                   int n_items) {
   extern __shared__ uint32_t lds[];
@@ -681,7 +861,7 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
   const int lane = threadIdx.x & 63;
   const int n_waves = gridDim.x * wpg;
   uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
-                   wave * Stage<CO>::wave_bytes;
+                   wave * wave_stage_bytes<SEL, CO, RECON, EV>();
   uint32_t* sweep = lds + wave * (64 * 65);
   int it = blockIdx.x * wpg + wave;
   if (it >= n_items) return;
@@ -699,7 +879,8 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
         chunk_load(planes[wn.plane], wn.t0, lane, nxt);
       }
       const Plane& P = planes[w.plane];
-      plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, cur, lane, sweep, stage);
+      plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane, sweep,
+                                      stage);
       if (!more) break;
       cur = nxt;
       w = wn;
@@ -711,7 +892,8 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
       const Plane& P = planes[w.plane];
       Pixels cur;
       chunk_load(P, w.t0, lane, cur);
-      plane_chunk<SEL, CO, RECON, EV>(P, tables[P.table], *scp, cur, lane, sweep, stage);
+      plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane, sweep,
+                                      stage);
     }
   }
 }
@@ -719,18 +901,16 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
 template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 2) void k_batch(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
-                                                  const ScaleConsts* __restrict__ scp,
                                                   const WorkItem* __restrict__ items, int n_items) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, scp, items, n_items);
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ planes,
                                                     const QuantConsts* __restrict__ tables,
-                                                    const ScaleConsts* __restrict__ scp,
                                                     const WorkItem* __restrict__ items,
                                                     int n_items) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, scp, items, n_items);
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,7 +918,7 @@ __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ pl
 // ---------------------------------------------------------------------------
 template <int KIND>
 __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, Plane P,
-                                                 QuantConsts qc, ScaleConsts sc) {
+                                                 QuantConsts qc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.nblocks) return;
   const int by = t / P.nbx, bx = t - by * P.nbx;
@@ -837,31 +1017,30 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
 // Host-side launchers
 // ---------------------------------------------------------------------------
 template <int SEL, int CO, bool RECON, int EV>
-static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, const ScaleConsts& sc,
-                                 int wpg, hipStream_t s) {
+static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg, hipStream_t s) {
   const int chunks = (P.nblocks + 127) / 128;
   const int grid = (chunks + wpg - 1) / wpg;
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
-                     (size_t)wpg * Stage<CO>::wave_bytes;
+                     (size_t)wpg * wave_stage_bytes<SEL, CO, RECON, EV>();
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
-    hipLaunchKernelGGL((k_plane_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
+    hipLaunchKernelGGL((k_plane_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc);
   else
-    hipLaunchKernelGGL((k_plane<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc, sc);
+    hipLaunchKernelGGL((k_plane<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, P, qc);
   return hipGetLastError();
 }
 
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
-                                 const ScaleConsts* scp, const WorkItem* items, int n_items,
+                                 const WorkItem* items, int n_items,
                                  int grid, int wpg, hipStream_t s) {
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
-                     (size_t)wpg * Stage<CO>::wave_bytes;
+                     (size_t)wpg * wave_stage_bytes<SEL, CO, RECON, EV>();
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, scp, items, n_items);
+                       tables, items, n_items);
   else
     hipLaunchKernelGGL((k_batch<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, scp, items, n_items);
+                       tables, items, n_items);
   return hipGetLastError();
 }
 
@@ -902,21 +1081,21 @@ static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
   RDCT_QEVAL_CASE2(FN, CO_I16, true, EV_COEF, __VA_ARGS__)
 
 hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
-                        const QuantConsts& qc, const ScaleConsts& sc, int wpg, hipStream_t s) {
+                        const QuantConsts& qc, int wpg, hipStream_t s) {
   if (P.nblocks <= 0) return hipSuccess;
-  RDCT_DISPATCH(launch_plane_t, P, qc, sc, wpg, s)
+  RDCT_DISPATCH(launch_plane_t, P, qc, wpg, s)
 }
 
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
-                        const QuantConsts* tables, const ScaleConsts* scp, const WorkItem* items,
+                        const QuantConsts* tables, const WorkItem* items,
                         int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  RDCT_DISPATCH(launch_batch_t, planes, tables, scp, items, n_items, grid, wpg, s)
+  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, grid, wpg, s)
 }
 
 hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height, int32_t r,
                           int32_t shift, float* dst, int64_t dpitch, const QuantConsts& qc,
-                          const ScaleConsts& sc, hipStream_t s) {
+                          hipStream_t s) {
   Plane P{};
   P.width = width;
   P.height = height;
@@ -931,11 +1110,11 @@ hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t hei
   if (P.nblocks <= 0) return hipSuccess;
   const dim3 grid((P.nblocks + 255) / 256), block(256);
   switch (kind) {
-    case INV_INT_I32: hipLaunchKernelGGL(k_inverse<INV_INT_I32>, grid, block, 0, s, coef, P, qc, sc); break;
-    case INV_INT_I16: hipLaunchKernelGGL(k_inverse<INV_INT_I16>, grid, block, 0, s, coef, P, qc, sc); break;
-    case INV_F32: hipLaunchKernelGGL(k_inverse<INV_F32>, grid, block, 0, s, coef, P, qc, sc); break;
-    case INV_Q_I32: hipLaunchKernelGGL(k_inverse<INV_Q_I32>, grid, block, 0, s, coef, P, qc, sc); break;
-    case INV_Q_I16: hipLaunchKernelGGL(k_inverse<INV_Q_I16>, grid, block, 0, s, coef, P, qc, sc); break;
+    case INV_INT_I32: hipLaunchKernelGGL(k_inverse<INV_INT_I32>, grid, block, 0, s, coef, P, qc); break;
+    case INV_INT_I16: hipLaunchKernelGGL(k_inverse<INV_INT_I16>, grid, block, 0, s, coef, P, qc); break;
+    case INV_F32: hipLaunchKernelGGL(k_inverse<INV_F32>, grid, block, 0, s, coef, P, qc); break;
+    case INV_Q_I32: hipLaunchKernelGGL(k_inverse<INV_Q_I32>, grid, block, 0, s, coef, P, qc); break;
+    case INV_Q_I16: hipLaunchKernelGGL(k_inverse<INV_Q_I16>, grid, block, 0, s, coef, P, qc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -118,7 +118,6 @@ struct rdct_server {
   int n_cu = 256;
   uint8_t* dev_base = nullptr;
   uint8_t* host_base = nullptr;
-  ScaleConsts* d_sc = nullptr;
   Arena dev, host;
   hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
   bool stream_busy[4] = {false, false, false, false};
@@ -241,7 +240,7 @@ hipError_t launch(rdct_server* s, Batch& b) {
   const int wpg = 4;
   const int grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2, (n_items + wpg - 1) / wpg));
   e = launch_batch(sel, CO_NONE, false, ev, reinterpret_cast<Plane*>(db + o_planes),
-                   reinterpret_cast<QuantConsts*>(db + o_tables), s->d_sc,
+                   reinterpret_cast<QuantConsts*>(db + o_tables),
                    reinterpret_cast<WorkItem*>(db + o_items), (int32_t)n_items, grid, wpg, st);
   if (e != hipSuccess) return e;
   if ((e = hipMemcpyAsync(hb + o_sse, dsse, 8 * (size_t)b.n_planes, hipMemcpyDeviceToHost, st)) !=
@@ -453,7 +452,6 @@ void destroy(rdct_server* s) {
       hipStreamSynchronize(s->streams[i]);
       hipStreamDestroy(s->streams[i]);
     }
-  if (s->d_sc) hipFree(s->d_sc);
   if (s->dev_base) hipFree(s->dev_base);
   if (s->host_base) hipHostFree(s->host_base);
   delete s;
@@ -480,18 +478,13 @@ rdct_status_t rdct_server_create(const rdct_server_cfg_t* cfg, rdct_server_t** o
   s->n_cu = device_cu_count();
   // The first 256 bytes of the device budget hold the plain path's error sum.
   if (hipMalloc(&s->dev_base, (size_t)s->cfg.budget_bytes) != hipSuccess ||
-      hipHostMalloc(&s->host_base, (size_t)s->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&s->d_sc, sizeof(ScaleConsts)) != hipSuccess) {
+      hipHostMalloc(&s->host_base, (size_t)s->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess) {
     destroy(s);
     return RDCT_ERR_NO_MEMORY;
   }
   s->dev.reset(s->cfg.budget_bytes, 256);
   s->dev.alloc(256);
   s->host.reset(s->cfg.staging_bytes, 256);
-  if (hipMemcpy(s->d_sc, &scale_consts(), sizeof(ScaleConsts), hipMemcpyHostToDevice) != hipSuccess) {
-    destroy(s);
-    return RDCT_ERR_HIP;
-  }
   for (int i = 0; i < s->cfg.n_streams; ++i)
     if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
       destroy(s);

@@ -233,6 +233,28 @@ def test_compress_eval_quant(h, w, quality):
     assert int(host(s2)[0]) == int(host(sse)[0])
 
 
+@pytest.mark.parametrize("pitch_extra,offset", [(8, 0), (3, 1), (0, 2)])
+def test_compress_eval_quant_recon_layouts(pitch_extra, offset):
+    # Whole-block plane (reconstruction staged through LDS), a short last chunk
+    # (200 blocks = 128 + 72), and reconstruction rows that are 16-byte aligned
+    # or not; the padding around the plane must stay untouched.
+    h, w = 64, 200
+    img = plane(h, w, seed=5)
+    res = O.quant_eval(img, O.quant_table(40))
+    sel = R.select(R.SEL_QUANT, quality=40, level_shift=128)
+    pitch = w + pitch_extra
+    buf = torch.full((h * pitch + offset + 16,), -12345.0, dtype=torch.float32, device=DEV)
+    view = buf[offset:offset + h * pitch].view(h, pitch)[:, :w]
+    sse, q, rec = R.compress_eval(g(img), sel, 1, R.COEF_I16, True, recon_out=view)
+    assert np.array_equal(host(q).astype(np.int64), flat(res["q"]))
+    assert np.max(np.abs(host(view) - res["recon"])) <= TOL
+    full = host(buf)
+    mask = np.ones(full.shape, dtype=bool)
+    idx = offset + np.arange(h)[:, None] * pitch + np.arange(w)[None, :]
+    mask[idx.ravel()] = False
+    assert np.all(full[mask] == -12345.0)
+
+
 def test_constant_plane_has_zero_retention_error():
     img = np.full((64, 64), 93, dtype=np.uint8)
     sse, _, _ = R.compress_eval(g(img), R.select(R.SEL_ZIGZAG, r=1), 45)
