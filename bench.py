@@ -26,11 +26,15 @@ N_CU = 256
 CLOCK_GHZ = 2.4
 # Integer VALU peak: 256 CUs x 64 lanes x 2.4 GHz (one 32-bit op per lane per clock).
 ALU_PEAK_TOPS = N_CU * 64 * CLOCK_GHZ / 1000.0
+# Published float64 vector peak of MI355X (an FMA counts as two operations).
+FP64_PEAK_TFLOPS = 78.6
 
 
 # Sources whose change invalidates a stored HBM-traffic record (the kernels,
 # their launch code and the build flags).
 KERNEL_SOURCES = ("paper_1402_6034_amd/csrc/rdct_kernels.hip",
+                  "paper_1402_6034_amd/csrc/rdct_quality.hip",
+                  "paper_1402_6034_amd/csrc/rdct_transforms.cpp",
                   "paper_1402_6034_amd/csrc/rdct_internal.h",
                   "paper_1402_6034_amd/csrc/rdct_tables.h",
                   "paper_1402_6034_amd/csrc/rdct_api.cpp",
@@ -101,6 +105,7 @@ class FrameQuant:
     256 MB last-level cache never holds the next launch's data."""
     name = "frame-8192-q50-fwd"
     workload_key = "frame"
+    dtype = "int16+f64"
     sets = 6
 
     def __init__(self, size=8192):
@@ -160,6 +165,7 @@ class PlainSweep:
     over r = 1..45, inverse error and per-plane PSNR; one launch per plane."""
     name = "plain-256x512x512-sweep-r1-45"
     workload_key = "sweep"
+    dtype = "int16+int64"
 
     def __init__(self, n=256, size=512):
         import torch
@@ -210,6 +216,95 @@ class PlainSweep:
                 "sample": f"{n} of the 256 planes, r = 1..45 each (inverse per r, exact SSE)"}
 
 
+class QualitySweep:
+    """The comparison of Section 3 at the paper's image size: 256 planes of
+    512 x 512, keep-r sweep over r = 1..45 under the exact DCT, the round-off
+    approximation and the signed DCT, scored per plane by MSE and by the mean
+    UQI over 8x8 windows; averaged over planes and given as the APE of each
+    approximation relative to the DCT.  One launch per transform (a device list
+    of 32 x 64 window tiles over all planes)."""
+    name = "quality-256x512x512-dct-rdct-sdct-r1-45"
+    workload_key = "quality"
+    dtype = "f64"
+    roofline_kind = "alu"
+    # Algorithmic float64 operations per pixel and r: reconstruction update 2
+    # (one FMA), squared error 3, the three sliding window sums 2 products + 12
+    # adds, the index formula and its two divisions about 14, and the forward
+    # transform (2048 per block over 45 values of r) about 1 -> 34.
+    flops_per_pixel_r = 34
+
+    def __init__(self, n=256, size=512, r_count=45):
+        from paper_1402_6034_amd import rdct as R, synth
+        self.R = R
+        self.n, self.size, self.r_count = n, size, r_count
+        log(f"[bench] rendering {n} planes {size}x{size}")
+        self.imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
+        self.transforms = [R.T_DCT, R.T_RDCT, R.T_SDCT]
+        self.plans = [R.QualityPlan(self.imgs, t, 1, r_count) for t in self.transforms]
+        self.nb1 = (size // 8) ** 2
+        self.summary = None
+
+    def launch(self, i=0):
+        self.plans[i % len(self.plans)].run()
+
+    kernel_launch = launch
+
+    def step(self):
+        import numpy as np
+        for p in self.plans:
+            p.run()
+        mets = [p.metrics() for p in self.plans]          # (mse, uqi), each (n, r)
+        mse = [m[0].mean(axis=0) for m in mets]
+        uqi = [m[1].mean(axis=0) for m in mets]
+        ape = {}
+        for j, nm in ((1, "rdct"), (2, "sdct")):
+            ape[nm] = {"mse": (100 * np.abs(mse[j] - mse[0]) / mse[0]).tolist(),
+                       "uqi": (100 * np.abs(uqi[j] - uqi[0]) / uqi[0]).tolist()}
+        self.summary = {"avg_mse": {"dct": mse[0].tolist(), "rdct": mse[1].tolist(),
+                                    "sdct": mse[2].tolist()},
+                        "avg_uqi": {"dct": uqi[0].tolist(), "rdct": uqi[1].tolist(),
+                                    "sdct": uqi[2].tolist()},
+                        "ape": ape}
+
+    blocks_per_step = property(lambda self: 3 * self.n * self.nb1)
+    # one launch covers one transform over every plane
+    flops_per_launch = property(lambda self: self.n * self.size * self.size * self.r_count
+                                * self.flops_per_pixel_r)
+
+    def config(self):
+        return {"workload": self.name, "planes": self.n, "plane": [self.size, self.size],
+                "r": [1, self.r_count], "transforms": ["dct", "rdct", "sdct"],
+                "metrics": ["mse", "uqi_8x8"], "launches_per_step": 3}
+
+    def report(self):
+        """APE at a few r (the full curves are in the summary)."""
+        if not self.summary:
+            return None
+        pick = [1, 5, 10, 20, 30, 45]
+        out = {}
+        for nm, a in self.summary["ape"].items():
+            out[nm] = {k: {str(r): round(a[k][r - 1], 4) for r in pick} for k in ("mse", "uqi")}
+        return {"ape_percent": out}
+
+    def cpu_baseline(self, budget_s):
+        import oracle as O
+        names = ["dct", "rdct", "sdct"]
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            img = self.imgs[n % self.n].cpu().numpy()
+            for nm in names:
+                O.quality_eval(img, nm, range(1, self.r_count + 1))
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": 3 * n * self.nb1 / dt / 1e6, "unit": "Mblocks/s",
+                "cores": _oracle_threads(), "kind": "oracle",
+                "sample": f"{n} of the 256 planes x 3 transforms, r = 1..{self.r_count} "
+                          "(reconstruction, SSE and 8x8-window UQI per r)"}
+
+
 class RaggedBatch:
     """1000 planes, width and height independently log-uniform in [64, 4096]
     (multiples of 8), quality uniform in 10..90: forward + S-scaled quantisation
@@ -218,6 +313,7 @@ class RaggedBatch:
     float32 reconstruction are written to HBM."""
     name = "ragged-1000-logU64-4096-q10-90"
     workload_key = "ragged"
+    dtype = "int16+f64"
 
     def __init__(self, n=1000, planes_cache=None, autotune=True):
         import numpy as np
@@ -368,7 +464,8 @@ def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
     return out
 
 
-WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch}
+WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch,
+             "quality": QualitySweep}
 
 
 def _oracle_threads():
@@ -386,8 +483,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="ragged: use the tuning cache (or defaults) instead of tuning first")
-    ap.add_argument("--serve-requests", type=int, default=4000,
-                    help="requests in the served trace (2000 req/s; 0 = skip the serving leg)")
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="requests in the served trace (2000 req/s; 0 = skip the serving leg; "
+                         "default 4000 with the ragged workload, else 0)")
     ap.add_argument("--planes-cache", default=None,
                     help="ragged: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -396,6 +494,8 @@ def main():
                     help="after the run, copy MIB mebibytes device-to-device 3 times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.serve_requests is None:
+        args.serve_requests = 4000 if args.workload == "ragged" else 0
     if args.gpus != 1:
         print("bench.py: this build measures one MI355X only; multi-GPU runs are not provided "
               "(the path would shard by plane; see the design notes).", file=sys.stderr)
@@ -427,15 +527,24 @@ def main():
     # Dominant kernel: average launch duration from HIP events.
     reps = max(20, args.steps)
     k_ms = event_time_ms(lambda i: wl.kernel_launch(i), reps)
-    nb = wl.blocks_per_step if not isinstance(wl, PlainSweep) else wl.nb1
-    alg_bytes = nb * wl.bytes_per_block
-    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     tr = traffic_record(wl.workload_key)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": tr["bytes"] if tr else None,
-                "kernel_ms": round(k_ms, 5), "bytes_per_launch": alg_bytes,
-                "kernel_source_sha256": kernel_source_hash()}
+    if getattr(wl, "roofline_kind", "hbm") == "alu":
+        flops = wl.flops_per_launch
+        achieved = flops / (k_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                    "traffic": tr["bytes"] if tr else None,
+                    "kernel_ms": round(k_ms, 5), "flops_per_launch": flops,
+                    "kernel_source_sha256": kernel_source_hash()}
+    else:
+        nb = wl.blocks_per_step if not isinstance(wl, PlainSweep) else wl.nb1
+        alg_bytes = nb * wl.bytes_per_block
+        achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": tr["bytes"] if tr else None,
+                    "kernel_ms": round(k_ms, 5), "bytes_per_launch": alg_bytes,
+                    "kernel_source_sha256": kernel_source_hash()}
     if tr:
         roofline["traffic_read"] = tr["read"]
         roofline["traffic_write"] = tr["write"]
@@ -461,10 +570,12 @@ def main():
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mblocks/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "int16+f64", "data": "synthetic", "config": wl.config(),
+           "dtype": wl.dtype, "data": "synthetic", "config": wl.config(),
            "roofline": roofline, "cpu_baseline": cpu}
     if plain is not None:
         out["plain"] = plain
+    if hasattr(wl, "report") and wl.report():
+        out["quality"] = wl.report()
     if serving is not None:
         out["serving"] = serving
     print(json.dumps(out), flush=True)

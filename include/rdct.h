@@ -214,6 +214,85 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
 void rdct_batch_plan_destroy(rdct_batch_plan_t* plan);
 
 /* ------------------------------------------------------------------------- */
+/* Comparison transforms and image-quality metrics (Sections 2-4)             */
+/* ------------------------------------------------------------------------- */
+
+/* An 8x8 transform T applied to every block as T A T^T (Section 3); the keep-r
+   reconstruction is A' = T^-1 (M_r . T A T^T) T^-T. */
+typedef enum {
+  RDCT_T_RDCT = 0,       /* C_orth = S C0, C0 = [2 C] (Section 2)                       */
+  RDCT_T_DCT = 1,        /* the exact DCT C, the reference of Section 3's comparison     */
+  RDCT_T_SDCT = 2,       /* signed DCT sign(C) / sqrt(8) (Section 2); not orthogonal:
+                            the inverse is the matrix inverse (8 sign(C)^-1 is integral) */
+  RDCT_T_RDCT_CEIL = 3,  /* (C0 C0^T)^(-1/2) C0 with C0 = ceil(2 C) (Section 4: ceiling in
+                            place of the round-off; C0 C0^T is a full matrix)            */
+  RDCT_T_RDCT_FLOOR = 4  /* C0 = floor(2 C): its first row is zero and C0 C0^T singular,
+                            so no approximation exists -- every call returns UNSUPPORTED */
+} rdct_transform_t;
+
+/*
+ * Keep-r sweep of one plane under one transform (Section 3), scored by SSE and
+ * by the universal quality index (UQI; the index of Wang and Bovik that
+ * Section 3 uses, evaluated over every 8x8 window at stride 1).  For every r in
+ * r_first .. r_first + r_count - 1 (1 <= r, last <= 64):
+ *   sse_out[i]  sum over the plane of (A - A'_r)^2 in units of
+ *               rdct_quality_sse_unit(transform): exact for RDCT (1/576^2) and
+ *               SDCT (1/64^2); for DCT and RDCT_CEIL float64 sums rounded to
+ *               2^-20 per 32 x 64 tile of windows.
+ *   uqi_out[i]  sum over the (H - 7)(W - 7) windows of
+ *               Q = [2 s_xy / (s_x^2 + s_y^2)] [2 xbar ybar / (xbar^2 + ybar^2)]
+ *               (a factor whose denominator is 0 counts as 1; so that float64
+               noise in exactly flat blocks cannot decide it, a reconstruction
+               window with variance <= 2^-24 grey levels^2 counts as flat and a
+               window mean of magnitude <= 2^-24 as 0), as int64 in units
+ *               of 2^-32 (float64 per tile, then rounded); mean UQI =
+ *               uqi_out * 2^-32 / rdct_quality_windows(width, height).  For RDCT and
+ *               SDCT the window sums are exact integers, so only the final
+ *               division of each window rounds.
+ * The reconstruction is real-valued (no rounding or clipping).  Width and height
+ * must be multiples of 8 (else UNSUPPORTED); planes up to 2^20 blocks.  Both
+ * outputs are device arrays of r_count entries, overwritten.  No allocation.
+ * Errors: INVALID_ARG, UNSUPPORTED (sizes, RDCT_T_RDCT_FLOOR), HIP.
+ */
+rdct_status_t rdct_quality_sweep(const uint8_t* src, int32_t width, int32_t height,
+                                 int64_t src_pitch, int32_t transform, int32_t r_first,
+                                 int32_t r_count, uint64_t* sse_out, int64_t* uqi_out,
+                                 void* stream);
+
+/* Units of rdct_quality_sweep's sse_out: 1/576^2 (RDCT), 1/64^2 (SDCT), 2^-20
+   (DCT, RDCT_CEIL); 0 for an invalid transform. */
+double rdct_quality_sse_unit(int32_t transform);
+
+/* Number of 8x8 windows at stride 1: (width - 7) * (height - 7), 0 if smaller. */
+int64_t rdct_quality_windows(int32_t width, int32_t height);
+
+/* One plane of a quality plan (DEVICE pointer, valid while the plan exists). */
+typedef struct {
+  const uint8_t* src;
+  int32_t width, height;
+  int64_t src_pitch;
+} rdct_quality_desc_t;
+
+typedef struct rdct_quality_plan rdct_quality_plan_t;
+
+/*
+ * Plan over n planes and one transform: every run computes rdct_quality_sweep
+ * for each plane in one launch (a device list of 32 x 64 window tiles).  Plane i
+ * writes sse_out[i * r_count + j] and uqi_out[i * r_count + j].  Allocates
+ * device memory (tile list and descriptors) -- not a hot call.
+ * Errors: as rdct_quality_sweep, plus NO_MEMORY.
+ */
+rdct_status_t rdct_quality_plan_create(const rdct_quality_desc_t* planes, int32_t n,
+                                       int32_t transform, int32_t r_first, int32_t r_count,
+                                       uint64_t* sse_out, int64_t* uqi_out,
+                                       rdct_quality_plan_t** out);
+
+/* Run the plan on `stream` (asynchronous; no allocation). */
+rdct_status_t rdct_quality_plan_run(rdct_quality_plan_t* plan, void* stream);
+
+void rdct_quality_plan_destroy(rdct_quality_plan_t* plan);
+
+/* ------------------------------------------------------------------------- */
 /* Compression server: admission by device-memory budget, continuous batching */
 /* ------------------------------------------------------------------------- */
 

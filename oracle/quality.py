@@ -29,6 +29,14 @@ Readings where the paper is silent (each is listed in the design notes):
     denominator is 0 (both windows flat, or both means zero).  The window is 8x8,
     sliding with stride 1 over the plane, (H - 7)(W - 7) windows; an image's UQI
     is the mean over its windows.
+  * Float64 noise must not decide the index.  A constant block keeps only its
+    DC term and is reconstructed exactly in real arithmetic, but the float64
+    transforms leave ~1e-13 of noise in it; in a flat or all-zero area that noise
+    alone would then set f_s or f_m.  So, in grey levels: a reconstruction window
+    whose variance (over N = 64 pixels) is at most 2^-24 counts as flat (s_y^2 =
+    s_xy = 0), a window mean |ybar| <= 2^-24 counts as 0, and a flat pixel window
+    has s_xy = 0.  Float64 noise stays three orders of magnitude below these
+    bounds.
   * The reconstruction is real-valued (no rounding or clipping), as for PSNR.
   * APE(m) = 100 |m_T - m_DCT| / |m_DCT|, on the averages over images.
 """
@@ -129,6 +137,7 @@ def sdct_numerators(img: np.ndarray, r: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 WIN = 8
+FLAT_EPS = 2.0 ** -24
 
 
 def uqi_map(x: np.ndarray, y: np.ndarray, win: int = WIN) -> np.ndarray:
@@ -148,6 +157,11 @@ def uqi_map(x: np.ndarray, y: np.ndarray, win: int = WIN) -> np.ndarray:
     vx = (dx * dx).sum(axis=(2, 3)) / n1
     vy = (dy * dy).sum(axis=(2, 3)) / n1
     cxy = (dx * dy).sum(axis=(2, 3)) / n1
+    flat_x = vx == 0
+    flat_y = vy * n1 / (win * win) <= FLAT_EPS
+    vy = np.where(flat_y, 0.0, vy)
+    cxy = np.where(flat_x | flat_y, 0.0, cxy)
+    my = np.where(np.abs(my) <= FLAT_EPS, 0.0, my)
     den_s = vx + vy
     den_m = mx * mx + my * my
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -159,6 +173,51 @@ def uqi_map(x: np.ndarray, y: np.ndarray, win: int = WIN) -> np.ndarray:
 def uqi(x: np.ndarray, y: np.ndarray, win: int = WIN) -> float:
     """Mean UQI over all win x win windows."""
     return float(np.mean(uqi_map(x, y, win)))
+
+
+def uqi_map_exact(x: np.ndarray, y_num: np.ndarray, d: int, win: int = WIN) -> np.ndarray:
+    """Q of every window for integer pixels x and a reconstruction given as
+    integer numerators y = y_num / d.  The window sums are exact (int64); the
+    degenerate-denominator rule is decided on exact integers, and only the
+    final two divisions round.  Same definition as uqi_map, with s_xy, s_x^2,
+    s_y^2 and the means written over N^2 d^2 as integer expressions."""
+    x = np.asarray(x, dtype=np.int64)
+    yn = np.asarray(y_num, dtype=np.int64)
+    n = win * win
+    sw = np.lib.stride_tricks.sliding_window_view
+
+    def wsum(a):
+        return sw(a, (win, win)).sum(axis=(2, 3))
+    sx, sxx = wsum(x), wsum(x * x)
+    sy, syy, sxy = wsum(yn), wsum(yn * yn), wsum(x * yn)
+    vx = n * sxx - sx * sx
+    vy = n * syy - sy * sy                    # n^2 d^2 var_y
+    # The flat-window rules on exact integers (the bounds n^2 d^2 2^-24 and
+    # n d 2^-24 are exact in float64).
+    flat_y = vy.astype(np.float64) <= n * n * d * d * FLAT_EPS
+    vy = np.where(flat_y, 0, vy)
+    cov = np.where((vx == 0) | flat_y, 0, n * sxy - sx * sy)
+    sy = np.where(np.abs(sy).astype(np.float64) <= n * d * FLAT_EPS, 0, sy)
+    num_s = 2 * d * cov
+    den_s = d * d * vx + vy
+    num_m = 2 * d * sx * sy
+    den_m = d * d * sx * sx + sy * sy
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f_s = np.where(den_s == 0, 1.0, num_s.astype(np.float64) / den_s.astype(np.float64))
+        f_m = np.where(den_m == 0, 1.0, num_m.astype(np.float64) / den_m.astype(np.float64))
+    return f_s * f_m
+
+
+def integer_numerators(img: np.ndarray, name: str, r: int) -> tuple[np.ndarray, int]:
+    """(numerator plane, d) of the keep-r reconstruction for the transforms whose
+    reconstruction is an integer over a fixed d: rdct (R / 576) and sdct (N / 64)."""
+    if name == "rdct":
+        h, w = np.asarray(img).shape
+        y = rdct.forward_blocks(image.tile(img))
+        return image.untile(rdct.retention_numerator(y, r), h, w), 576
+    if name == "sdct":
+        return sdct_numerators(img, r), 64
+    raise ValueError(f"{name} has no integer numerator")
 
 
 def uqi_window_exact(xw, yw):
@@ -173,6 +232,13 @@ def uqi_window_exact(xw, yw):
     vx = sum((v - mx) ** 2 for v in xs) / (n - 1)
     vy = sum((v - my) ** 2 for v in ys) / (n - 1)
     cxy = sum((a - mx) * (b - my) for a, b in zip(xs, ys)) / (n - 1)
+    flat_y = vy * (n - 1) / n <= Fraction(FLAT_EPS)
+    if flat_y:
+        vy = Fraction(0)
+    if vx == 0 or flat_y:
+        cxy = Fraction(0)
+    if abs(my) <= Fraction(FLAT_EPS):
+        my = Fraction(0)
     f_s = Fraction(1) if vx + vy == 0 else 2 * cxy / (vx + vy)
     f_m = Fraction(1) if mx * mx + my * my == 0 else 2 * mx * my / (mx * mx + my * my)
     return f_s * f_m
@@ -207,5 +273,5 @@ def ape(value: float, reference: float) -> float:
 
 
 __all__ = ["TRANSFORMS", "round_variant_matrix", "transform", "sdct_integer_inverse",
-           "retention_recon", "sdct_numerators", "uqi_map", "uqi", "uqi_window_exact",
-           "quality_eval", "ape", "WIN"]
+           "retention_recon", "sdct_numerators", "uqi_map", "uqi", "uqi_map_exact",
+           "integer_numerators", "uqi_window_exact", "quality_eval", "ape", "WIN"]

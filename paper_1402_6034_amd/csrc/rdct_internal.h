@@ -39,6 +39,40 @@ struct QuantConsts {
   int32_t qi[64];
 };
 
+// Comparison transforms: forward matrix F (block -> F A F^T) and inverse basis
+// G with scale D (keep-r reconstruction G (M . Y) G^T / D); `exact` when F, G
+// and D are integers.
+struct TransformTables {
+  double F[64];
+  double G[64];
+  double D;
+  int32_t exact;
+};
+rdct_status_t build_transform(int id, TransformTables* out);
+
+// Quality sweep: plane descriptor, tile work item and kernel constants.
+struct QPlane {
+  const uint8_t* src;
+  int64_t pitch;
+  int32_t width, height;     // multiples of 8
+  int32_t tiles_x, tiles_y;  // tiles of 32 x 64 windows
+  uint64_t* sse;             // r_count accumulators
+  int64_t* uqi;              // r_count accumulators (2^-32 units)
+};
+struct QTile {
+  int32_t plane;
+  int32_t tile;              // ty * tiles_x + tx
+};
+struct QualityArgs {
+  TransformTables T;
+  int32_t r_first, r_count;
+};
+int quality_tiles_x(int width);
+int quality_tiles_y(int height);
+hipError_t launch_quality(const QPlane& P, const QualityArgs& A, hipStream_t stream);
+hipError_t launch_quality_batch(const QPlane* planes, const QTile* tiles, int32_t n_tiles,
+                                const QualityArgs& A, hipStream_t stream);
+
 enum SelKind { SEL_ZZ = 0, SEL_Q = 1 };
 enum CoefKind { CO_NONE = 0, CO_I32 = 1, CO_I16 = 2, CO_F32 = 3 };
 // EV_SPATIAL: squared error from the reconstruction, pixel by pixel.

@@ -102,6 +102,12 @@ class Tuning(ctypes.Structure):
                 ("reserved", c_int32)]
 
 
+class QualityDesc(ctypes.Structure):
+    """rdct_quality_desc_t."""
+    _fields_ = [("src", c_void_p), ("width", c_int32), ("height", c_int32),
+                ("src_pitch", c_int64)]
+
+
 def _declare_extra(L):
     """Signatures of the batch and server entry points."""
     P = c_void_p
@@ -116,6 +122,20 @@ def _declare_extra(L):
     L.rdct_batch_autotune.restype = c_int32
     L.rdct_batch_plan_destroy.argtypes = [P]
     L.rdct_batch_plan_destroy.restype = None
+    L.rdct_quality_sweep.argtypes = [P, c_int32, c_int32, c_int64, c_int32, c_int32, c_int32, P, P,
+                                     P]
+    L.rdct_quality_sweep.restype = c_int32
+    L.rdct_quality_sse_unit.argtypes = [c_int32]
+    L.rdct_quality_sse_unit.restype = c_double
+    L.rdct_quality_windows.argtypes = [c_int32, c_int32]
+    L.rdct_quality_windows.restype = c_int64
+    L.rdct_quality_plan_create.argtypes = [POINTER(QualityDesc), c_int32, c_int32, c_int32, c_int32,
+                                           P, P, POINTER(c_void_p)]
+    L.rdct_quality_plan_create.restype = c_int32
+    L.rdct_quality_plan_run.argtypes = [P, P]
+    L.rdct_quality_plan_run.restype = c_int32
+    L.rdct_quality_plan_destroy.argtypes = [P]
+    L.rdct_quality_plan_destroy.restype = None
     if hasattr(L, "rdct_server_create"):
         from . import serve as _serve
         _serve.declare(L)
@@ -325,6 +345,100 @@ class BatchPlan:
     def close(self):
         if self.handle:
             rdct_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Comparison transforms and quality metrics (rdct_quality_*)
+# ---------------------------------------------------------------------------
+
+T_RDCT, T_DCT, T_SDCT, T_RDCT_CEIL, T_RDCT_FLOOR = range(5)
+UQI_UNIT = 2.0 ** -32
+
+
+def rdct_quality_sweep(src, width, height, pitch, transform, r_first, r_count, sse_out, uqi_out,
+                       stream=None):
+    _check(lib().rdct_quality_sweep(_ptr(src), width, height, pitch, transform, r_first, r_count,
+                                    _ptr(sse_out), _ptr(uqi_out), _stream(stream)),
+           "rdct_quality_sweep")
+
+
+def rdct_quality_sse_unit(transform):
+    return lib().rdct_quality_sse_unit(transform)
+
+
+def rdct_quality_windows(width, height):
+    return lib().rdct_quality_windows(width, height)
+
+
+def quality_sweep(img: torch.Tensor, transform: int, r_first: int = 1, r_count: int = 45,
+                  stream=None):
+    """Raw (sse, uqi) int64 tensors of r_count entries for one device plane."""
+    w, h, pitch = _plane_args(img)
+    sse = torch.empty(r_count, dtype=torch.int64, device=img.device)
+    uqi = torch.empty(r_count, dtype=torch.int64, device=img.device)
+    rdct_quality_sweep(img, w, h, pitch, transform, r_first, r_count, sse, uqi, stream)
+    return sse, uqi
+
+
+def quality_metrics(sse_raw, uqi_raw, transform, height, width):
+    """MSE and mean UQI (float64 numpy arrays) from raw sums."""
+    import numpy as np
+    unit = rdct_quality_sse_unit(transform)
+    mse = np.asarray(sse_raw, dtype=np.float64) * unit / (height * width)
+    uqi = np.asarray(uqi_raw, dtype=np.float64) * UQI_UNIT / rdct_quality_windows(width, height)
+    return mse, uqi
+
+
+class QualityPlan:
+    """Keep-r sweep of many device planes under one transform in one launch per
+    run; sse and uqi are (n, r_count) int64 tensors of raw sums."""
+
+    def __init__(self, planes, transform, r_first=1, r_count=45):
+        if not planes:
+            raise ValueError("no planes")
+        self.planes = list(planes)
+        self.n = len(planes)
+        self.transform, self.r_first, self.r_count = transform, r_first, r_count
+        dev = planes[0].device
+        self.sse = torch.empty((self.n, r_count), dtype=torch.int64, device=dev)
+        self.uqi = torch.empty((self.n, r_count), dtype=torch.int64, device=dev)
+        descs = (QualityDesc * self.n)()
+        for i, img in enumerate(self.planes):
+            w, h, pitch = _plane_args(img)
+            descs[i].src, descs[i].width, descs[i].height, descs[i].src_pitch = (
+                img.data_ptr(), w, h, pitch)
+        self._descs = descs
+        hdl = c_void_p()
+        _check(lib().rdct_quality_plan_create(descs, self.n, transform, r_first, r_count,
+                                              _ptr(self.sse), _ptr(self.uqi), ctypes.byref(hdl)),
+               "rdct_quality_plan_create")
+        self.handle = hdl
+
+    def run(self, stream=None):
+        _check(lib().rdct_quality_plan_run(self.handle, _stream(stream)), "rdct_quality_plan_run")
+
+    def metrics(self):
+        """(mse, uqi) float64 numpy arrays of shape (n, r_count)."""
+        import numpy as np
+        torch.cuda.synchronize()
+        sse, uqi = self.sse.cpu().numpy(), self.uqi.cpu().numpy()
+        mse = np.empty(sse.shape)
+        mu = np.empty(uqi.shape)
+        for i, img in enumerate(self.planes):
+            h, w = img.shape
+            mse[i], mu[i] = quality_metrics(sse[i], uqi[i], self.transform, h, w)
+        return mse, mu
+
+    def close(self):
+        if self.handle:
+            lib().rdct_quality_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -134,3 +134,43 @@ def test_batch_plan_create_rejects():
     assert L.rdct_batch_plan_create(arr, 0, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
     assert L.rdct_batch_run(None, None) == R.ERR_INVALID_ARG
     assert L.rdct_batch_autotune(None, 3, None, None) == R.ERR_INVALID_ARG
+
+
+def test_quality_units_and_windows():
+    assert R.rdct_quality_sse_unit(R.T_RDCT) == 1.0 / 576 ** 2
+    assert R.rdct_quality_sse_unit(R.T_SDCT) == 1.0 / 64 ** 2
+    assert R.rdct_quality_sse_unit(R.T_DCT) == 2.0 ** -20
+    assert R.rdct_quality_sse_unit(R.T_RDCT_CEIL) == 2.0 ** -20
+    assert R.rdct_quality_sse_unit(9) == 0.0
+    assert R.rdct_quality_windows(512, 512) == 505 * 505
+    assert R.rdct_quality_windows(8, 16) == 9
+    assert R.rdct_quality_windows(7, 100) == 0
+
+
+@needs_no_gpu
+def test_quality_sweep_rejects():
+    L = R.lib()
+
+    def call(w=64, h=64, pitch=64, t=R.T_RDCT, r0=1, n=45, sse=FAKE_SSE, uqi=FAKE_DST, src=FAKE_SRC):
+        return L.rdct_quality_sweep(src, w, h, pitch, t, r0, n, sse, uqi, None)
+    assert call(src=None) == R.ERR_INVALID_ARG
+    assert call(sse=None) == R.ERR_INVALID_ARG
+    assert call(uqi=FAKE_DST + 4) == R.ERR_INVALID_ARG
+    assert call(t=9) == R.ERR_INVALID_ARG
+    assert call(r0=0) == R.ERR_INVALID_ARG
+    assert call(r0=20, n=46) == R.ERR_INVALID_ARG
+    assert call(n=0) == R.ERR_INVALID_ARG
+    assert call(pitch=63) == R.ERR_INVALID_ARG
+    assert call(t=R.T_RDCT_FLOOR) == R.ERR_UNSUPPORTED      # floor(2C): singular
+    assert call(w=60) == R.ERR_UNSUPPORTED                   # needs whole blocks
+    assert call(w=8192, h=8200, pitch=8192) == R.ERR_UNSUPPORTED  # above 2^20 blocks
+    h = ctypes.c_void_p()
+    d = (R.QualityDesc * 2)()
+    for x in d:
+        x.src, x.width, x.height, x.src_pitch = FAKE_SRC, 64, 64, 64
+    d[1].width = 12
+    assert L.rdct_quality_plan_create(d, 2, R.T_DCT, 1, 45, FAKE_SSE, FAKE_DST, ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    d[1].width = 64
+    assert L.rdct_quality_plan_create(d, 2, R.T_RDCT_FLOOR, 1, 45, FAKE_SSE, FAKE_DST, ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    assert L.rdct_quality_plan_create(d, 0, R.T_DCT, 1, 45, FAKE_SSE, FAKE_DST, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    assert L.rdct_quality_plan_run(None, None) == R.ERR_INVALID_ARG

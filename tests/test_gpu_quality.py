@@ -1,0 +1,173 @@
+"""Comparison path (rdct_quality_*) against the oracle: keep-r SSE and mean UQI
+of the round-off approximation, the exact DCT, the signed DCT and the ceiling
+variant, for every r of a sweep.
+
+Bars: SSE bit-exact for the transforms with integer numerators (round-off:
+units 1/576^2, signed DCT: 1/64^2); float transforms within one 2^-21 per
+32 x 64 tile plus 1e-9 relative.  Mean UQI within the output's
+fixed-point step (2^-33 per tile, averaged over the windows) plus 1e-12 of the
+exact-integer oracle (round-off, signed DCT), or plus 1e-9 of the float64
+oracle (DCT, ceiling) on planes with no flat window, where float64 sums are
+well conditioned.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1402_6034_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+R = pytest.importorskip("paper_1402_6034_amd.rdct")
+DEV = "cuda:0"
+NAMES = {R.T_RDCT: "rdct", R.T_DCT: "dct", R.T_SDCT: "sdct", R.T_RDCT_CEIL: "rdct_ceil"}
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def n_tiles(h, w):
+    return -(-h // 32) * -(-w // 64)
+
+
+def check(img, t, r_first, r_count, sse_raw, uqi_raw):
+    name = NAMES[t]
+    h, w = img.shape
+    rs = list(range(r_first, r_first + r_count))
+    nwin = (h - 7) * (w - 7)
+    # Each tile's UQI sum is rounded to 2^-32 before it is added.
+    quant = n_tiles(h, w) * 2.0 ** -33 / nwin
+    x = img.astype(np.int64)
+    for i, r in enumerate(rs):
+        if t in (R.T_RDCT, R.T_SDCT):
+            num, d = O.integer_numerators(img, name, r)
+            assert int(sse_raw[i]) == int(np.sum((d * x - num) ** 2)), (name, r)
+            want_u = float(np.mean(O.uqi_map_exact(x, num, d)))
+            tol_u = quant + 1e-12
+        else:
+            rec = O.retention_recon(img, name, r)
+            sse = float(np.sum((x - rec) ** 2))
+            got = int(sse_raw[i]) * 2.0 ** -20
+            assert abs(got - sse) <= n_tiles(h, w) * 2.0 ** -21 + 1e-9 * sse, (name, r)
+            want_u = O.uqi(x, rec)
+            tol_u = quant + 1e-9
+        got_u = int(uqi_raw[i]) * 2.0 ** -32 / nwin
+        assert abs(got_u - want_u) <= tol_u, (name, r, got_u, want_u)
+
+
+def no_flat_windows(img):
+    v = np.lib.stride_tricks.sliding_window_view(img.astype(np.float64), (8, 8)).var(axis=(2, 3))
+    return bool(np.all(v > 0))
+
+
+@pytest.mark.parametrize("t", [R.T_RDCT, R.T_DCT, R.T_SDCT, R.T_RDCT_CEIL])
+@pytest.mark.parametrize("h,w", [(8, 8), (40, 48), (72, 136), (32, 64), (96, 200)])
+def test_sweep_matches_oracle(t, h, w):
+    img = synth.render_np(100 + h + w, h, w)
+    assert no_flat_windows(img)
+    r_first, r_count = (1, 45) if h * w <= 72 * 136 else (3, 12)
+    sse, uqi = R.quality_sweep(g(img), t, r_first, r_count)
+    check(img, t, r_first, r_count, host(sse), host(uqi))
+
+
+@pytest.mark.parametrize("t", [R.T_RDCT, R.T_DCT])
+def test_full_retention_and_last_positions(t):
+    img = synth.render_np(7, 40, 72)
+    sse, uqi = R.quality_sweep(g(img), t, 60, 5)
+    check(img, t, 60, 5, host(sse), host(uqi))
+    # r = 64 reconstructs exactly: zero error, UQI 1 in every window.
+    assert int(host(sse)[-1]) <= (0 if t == R.T_RDCT else n_tiles(40, 72))
+    assert abs(int(host(uqi)[-1]) * 2.0 ** -32 / ((40 - 7) * (72 - 7)) - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("t", [R.T_RDCT, R.T_SDCT, R.T_DCT, R.T_RDCT_CEIL])
+def test_flat_regions(t):
+    # Constant areas give flat windows: the integer transforms decide the
+    # degenerate factors exactly, the float ones through the flat-window rule,
+    # as the oracle does.
+    img = synth.render_np(3, 48, 64)
+    img[8:40, 0:40] = 200
+    img[:, 56:] = 0
+    img[40:, :16] = 255
+    sse, uqi = R.quality_sweep(g(img), t, 1, 45)
+    check(img, t, 1, 45, host(sse), host(uqi))
+
+
+def test_pitched_plane():
+    img = synth.render_np(9, 64, 64)
+    buf = torch.zeros((64, 80), dtype=torch.uint8, device=DEV)
+    buf[:, :64] = g(img)
+    sse, uqi = R.quality_sweep(buf[:, :64], R.T_SDCT, 1, 10)
+    check(img, R.T_SDCT, 1, 10, host(sse), host(uqi))
+
+
+def test_plan_equals_single_calls():
+    shapes = [(64, 64), (40, 136), (8, 8), (96, 72), (32, 256)]
+    imgs = [synth.render_np(200 + i, h, w) for i, (h, w) in enumerate(shapes)]
+    dev = [g(a) for a in imgs]
+    for t in (R.T_RDCT, R.T_DCT, R.T_SDCT):
+        plan = R.QualityPlan(dev, t, 2, 20)
+        for _ in range(2):        # a second run overwrites, it does not accumulate
+            plan.run()
+        sse, uqi = host(plan.sse), host(plan.uqi)
+        for i, d in enumerate(dev):
+            s1, u1 = R.quality_sweep(d, t, 2, 20)
+            assert np.array_equal(host(s1), sse[i])
+            assert np.array_equal(host(u1), uqi[i])
+        plan.close()
+
+
+def test_unsupported_cases_raise():
+    img = g(synth.render_np(1, 64, 64))
+    with pytest.raises(R.RdctError) as e:
+        R.quality_sweep(img, R.T_RDCT_FLOOR, 1, 45)
+    assert e.value.status == R.ERR_UNSUPPORTED
+    with pytest.raises(R.RdctError) as e:
+        R.quality_sweep(g(synth.render_np(1, 60, 64)), R.T_RDCT, 1, 45)
+    assert e.value.status == R.ERR_UNSUPPORTED
+
+
+def test_dct_beats_approximations_and_ape():
+    # Section 3's comparison on a few planes: MSE of the exact DCT is the
+    # smallest for every r (energy compaction), and the APE values of the
+    # round-off approximation computed from the GPU metrics equal the oracle's.
+    imgs = [synth.render_np(300 + i, 64, 64) for i in range(3)]
+    dev = [g(a) for a in imgs]
+    res = {}
+    for t in (R.T_DCT, R.T_RDCT, R.T_SDCT):
+        plan = R.QualityPlan(dev, t, 1, 45)
+        plan.run()
+        res[t] = plan.metrics()
+        plan.close()
+    mse_dct, uqi_dct = res[R.T_DCT][0].mean(axis=0), res[R.T_DCT][1].mean(axis=0)
+    for t in (R.T_RDCT, R.T_SDCT):
+        assert np.all(res[t][0].mean(axis=0)[1:] >= mse_dct[1:] - 1e-9)
+    ape = [O.ape(m, d) for m, d in zip(res[R.T_RDCT][0].mean(axis=0), mse_dct)]
+    ref = {n: [O.quality_eval(a, n, [5, 20]) for a in imgs] for n in ("dct", "rdct")}
+    for j, r in ((4, 5), (19, 20)):
+        want = O.ape(np.mean([q["mse"][r] for q in ref["rdct"]]),
+                     np.mean([q["mse"][r] for q in ref["dct"]]))
+        assert abs(ape[j] - want) < 1e-6
+
+
+def test_paper_size_plane_and_dc_only_agreement():
+    # A 512 x 512 plane (the paper's image size, several saturated flat areas)
+    # at a few r; at r = 1 every transform keeps the DC row and the
+    # reconstructions (hence MSE and UQI) coincide.
+    img = synth.render_np(88, 512, 512)          # about half of it saturates at 0
+    uqi1 = {}
+    for t in (R.T_DCT, R.T_RDCT, R.T_SDCT):
+        for r in (1, 10, 45):
+            sse, uqi = R.quality_sweep(g(img), t, r, 1)
+            check(img, t, r, 1, host(sse), host(uqi))
+            if r == 1:
+                uqi1[t] = int(host(uqi)[0]) * 2.0 ** -32 / (505 * 505)
+    assert abs(uqi1[R.T_DCT] - uqi1[R.T_RDCT]) < 1e-9
+    assert abs(uqi1[R.T_SDCT] - uqi1[R.T_RDCT]) < 1e-9

@@ -158,6 +158,35 @@ def test_uqi_flat_windows():
     assert O.uqi_map(x, v)[0, 0] == 0.0
 
 
+def test_uqi_flat_reconstruction_rule():
+    # A flat pixel window against a reconstruction that is flat up to float64
+    # noise counts as two flat windows; a real variation does not.
+    x = np.full((8, 8), 200.0)
+    noisy = x + 1e-11 * np.random.default_rng(1).standard_normal((8, 8))
+    assert O.uqi_map(x, noisy)[0, 0] == pytest.approx(1.0, abs=1e-12)
+    varied = x + 0.05 * np.random.default_rng(2).standard_normal((8, 8))
+    assert O.uqi_map(x, varied)[0, 0] == 0.0
+    assert O.uqi_window_exact(x, noisy) == pytest.approx(1.0, abs=1e-12)
+    # All-zero pixels against a reconstruction that is zero up to noise: both
+    # means are 0 and both windows flat -> 1.
+    z = np.zeros((8, 8))
+    assert O.uqi_map(z, 1e-13 * np.random.default_rng(3).standard_normal((8, 8)))[0, 0] == 1.0
+
+
+def test_dc_only_uqi_is_the_same_for_dct_and_rdct_with_flat_regions():
+    # r = 1 keeps the DC row, which the DCT and C_orth share (Section 2): the
+    # reconstructions agree, and so must the index, flat regions included.
+    img = _img(16, 48, 64)
+    img[8:40, 0:40] = 255
+    img[0:16, 48:64] = 0
+    x = img.astype(np.int64)
+    num, d = O.integer_numerators(img, "rdct", 1)
+    exact = O.uqi_map_exact(x, num, d)
+    flt = O.uqi_map(x, O.retention_recon(img, "dct", 1))
+    assert np.max(np.abs(exact - flt)) < 1e-12
+    assert np.sum(exact == 1.0) > 0          # some windows are flat in both images
+
+
 def test_uqi_matches_exact_rationals():
     rng = np.random.default_rng(11)
     x = rng.integers(0, 256, size=(10, 11))
@@ -167,6 +196,38 @@ def test_uqi_matches_exact_rationals():
         for j in range(m.shape[1]):
             q = O.uqi_window_exact(x[i:i + 8, j:j + 8], y[i:i + 8, j:j + 8])
             assert abs(m[i, j] - float(q)) < 1e-12
+
+
+def test_exact_uqi_matches_rationals_and_float_uqi():
+    rng = np.random.default_rng(14)
+    x = rng.integers(0, 256, size=(11, 10))
+    y_num = 576 * x + rng.integers(-9000, 9000, size=x.shape)
+    ex = O.uqi_map_exact(x, y_num, 576)
+    from fractions import Fraction
+    for i in range(ex.shape[0]):
+        for j in range(ex.shape[1]):
+            yw = [Fraction(int(v), 576) for v in y_num[i:i + 8, j:j + 8].ravel()]
+            q = O.uqi_window_exact(x[i:i + 8, j:j + 8], np.array(yw, dtype=object))
+            assert abs(ex[i, j] - float(q)) < 1e-14
+    assert np.allclose(ex, O.uqi_map(x, y_num / 576.0), atol=1e-12)
+
+
+def test_exact_uqi_flat_windows_are_one():
+    # A constant plane keeps only its DC: the reconstruction is the plane itself,
+    # every window is flat in both images with equal means -> Q = 1 exactly.
+    img = np.full((24, 32), 77, dtype=np.uint8)
+    for name in ("rdct", "sdct"):
+        num, d = O.integer_numerators(img, name, 1)
+        assert np.array_equal(num, d * img.astype(np.int64))
+        assert np.all(O.uqi_map_exact(img, num, d) == 1.0)
+
+
+@pytest.mark.parametrize("name", ["rdct", "sdct"])
+def test_integer_numerators_equal_float_reconstruction(name):
+    img = _img(15, 24, 40)
+    for r in (1, 7, 30):
+        num, d = O.integer_numerators(img, name, r)
+        assert np.max(np.abs(num / d - O.retention_recon(img, name, r))) < 1e-10
 
 
 def test_uqi_symmetric_and_bounded():
