@@ -17,3 +17,4 @@ from .rdct import *  # noqa: F401,F403
 from .image import *  # noqa: F401,F403
 from .spectral import *  # noqa: F401,F403
 from .quality import *  # noqa: F401,F403
+from .codec import *  # noqa: F401,F403

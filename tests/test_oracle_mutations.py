@@ -141,3 +141,29 @@ def test_transposed_retention_mask_is_caught(monkeypatch):
         return O.untile(np.matmul(np.matmul(ti, y), ti.T), h, w)
     monkeypatch.setattr(Q, "retention_recon", bad)
     _fails(QP.test_dct_sse_is_parseval_of_dropped_coefficients)
+
+
+# --- codec output ------------------------------------------------------------
+
+import oracle.codec as CD  # noqa: E402
+import test_oracle_codec_pins as CP  # noqa: E402
+
+
+def test_run_off_by_one_is_caught(monkeypatch):
+    def bad(values):
+        pairs, run = [], 0
+        for v in values:
+            run += 1
+            if int(v) != 0:
+                pairs.append((run, int(v)))
+                run = 0
+        return pairs
+    monkeypatch.setattr(O, "rle_encode", bad)
+    _fails(CP.test_rle_hand_examples)
+
+
+def test_half_even_pixel_rounding_is_caught(monkeypatch):
+    def bad(r_num):
+        return np.clip(np.rint(np.asarray(r_num) / 576.0), 0, 255).astype(np.uint8)
+    monkeypatch.setattr(O, "u8_from_numerator", bad)
+    _fails(CP.test_u8_rounding_is_half_away_and_clamped)
