@@ -34,6 +34,8 @@ FP64_PEAK_TFLOPS = 78.6
 # their launch code and the build flags).
 KERNEL_SOURCES = ("paper_1402_6034_amd/csrc/rdct_kernels.hip",
                   "paper_1402_6034_amd/csrc/rdct_quality.hip",
+                  "paper_1402_6034_amd/csrc/rdct_codec.hip",
+                  "paper_1402_6034_amd/csrc/rdct_device.h",
                   "paper_1402_6034_amd/csrc/rdct_transforms.cpp",
                   "paper_1402_6034_amd/csrc/rdct_internal.h",
                   "paper_1402_6034_amd/csrc/rdct_tables.h",
@@ -214,6 +216,76 @@ class PlainSweep:
         return {"value": n * self.nb1 / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
                 "kind": "oracle",
                 "sample": f"{n} of the 256 planes, r = 1..45 each (inverse per r, exact SSE)"}
+
+
+class CodecFrame:
+    """Codec output of one 8192 x 8192 frame at quality 50: transform, exact
+    quantisation, zig-zag run-length pairs of every block and the 8-bit
+    reconstruction (encode), then the packed stream with block offsets (pack).
+    Four buffer sets rotate so the 256 MB last-level cache never holds the next
+    launch's data."""
+    name = "codec-frame-8192-q50-rle-u8"
+    workload_key = "codec"
+    dtype = "int32+f64"
+    sets = 4
+
+    def __init__(self, size=8192):
+        from paper_1402_6034_amd import rdct as R, synth
+        self.R = R
+        self.size = size
+        self.nb = (size // 8) ** 2
+        log(f"[bench] rendering {size}x{size} frame")
+        frame = synth.render(0, size, size, device="cuda")
+        self.frames = [frame] + [frame.clone() for _ in range(self.sets - 1)]
+        self.codecs = [R.Codec(size, size, "cuda") for _ in range(self.sets)]
+        self.sel = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+        self.i = 0
+        self.launch(0)
+        self.codecs[0].pack()
+        import torch
+        torch.cuda.synchronize()
+        self.pairs = int(self.codecs[0].offsets[-1])
+        log(f"[bench] {self.pairs} pairs ({self.pairs / self.nb:.2f} per block)")
+
+    def launch(self, i=None):
+        k = self.i if i is None else i % self.sets
+        self.codecs[k].encode(self.frames[k], self.sel)
+        self.i = (self.i + 1) % self.sets
+
+    kernel_launch = launch
+
+    def step(self):
+        k = self.i
+        self.launch()
+        self.codecs[k].pack()
+
+    blocks_per_step = property(lambda self: self.nb)
+    # encode: 64 B of pixels in, 64 B of 8-bit pixels, a 2-byte count and 4 B per
+    # pair out (the dominant kernel); the pairs per block are measured.
+    bytes_per_block = property(lambda self: 64 + 64 + 2 + 4 * self.pairs / self.nb)
+
+    def config(self):
+        return {"workload": self.name, "frame": [self.size, self.size], "blocks": self.nb,
+                "quality": 50, "level_shift": 128, "pairs": self.pairs,
+                "outputs": ["rle_pairs_int32", "offsets_uint32", "recon_u8"]}
+
+    def cpu_baseline(self, budget_s):
+        import oracle as O
+        img = self.frames[0].cpu().numpy()
+        t0 = time.perf_counter()
+        n, rows = 0, 64
+        while True:
+            y0 = (n * rows) % self.size
+            O.codec_encode(img[y0:y0 + rows], "quant", quality=50, level_shift=128)
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        blocks = n * (rows // 8) * (self.size // 8)
+        return {"value": blocks / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
+                "kind": "oracle",
+                "sample": f"{n} bands of {rows}x{self.size} px ({blocks} blocks): quantise, "
+                          "run-length pairs, 8-bit reconstruction"}
 
 
 class QualitySweep:
@@ -465,7 +537,7 @@ def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
 
 
 WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch,
-             "quality": QualitySweep}
+             "quality": QualitySweep, "codec": CodecFrame}
 
 
 def _oracle_threads():
@@ -538,7 +610,7 @@ def main():
                     "kernel_source_sha256": kernel_source_hash()}
     else:
         nb = wl.blocks_per_step if not isinstance(wl, PlainSweep) else wl.nb1
-        alg_bytes = nb * wl.bytes_per_block
+        alg_bytes = int(round(nb * wl.bytes_per_block))
         achieved = alg_bytes / (k_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -214,6 +214,49 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
 void rdct_batch_plan_destroy(rdct_batch_plan_t* plan);
 
 /* ------------------------------------------------------------------------- */
+/* Codec output: run-length coded kept coefficients and 8-bit pixels          */
+/* ------------------------------------------------------------------------- */
+
+/* Number of 64-block groups of a plane: ceil(ceil(W/8) ceil(H/8) / 64). */
+int64_t rdct_codec_groups(int32_t width, int32_t height);
+
+/*
+ * Store what Section 3's procedure keeps: for every block, the kept
+ * coefficients in zig-zag order as (run, value) pairs -- run = zeros before a
+ * non-zero value, trailing zeros implied by the pair count, the DC coded like
+ * the rest -- and optionally the 8-bit reconstruction clamp(round(A'), 0, 255)
+ * (round half away from zero).
+ *   sel         ZIGZAG: ranks 0 .. r-1 of Y are kept (NONE: all 64); the pixels
+ *               come from the exact numerator, floor((R + 288) / 576).  QUANT: all
+ *               64 values q are kept; A' in float64 plus the level shift.
+ *   counts      device, ceil(W/8) ceil(H/8) uint16: pairs per block.
+ *   group_pairs device, rdct_codec_groups uint32: pairs per 64-block group.
+ *   slots       device, rdct_codec_groups * 4096 int32: group g's pairs, in block
+ *               order, at slots + 4096 g.  A pair is (run << 16) | (uint16)value
+ *               (|Y| <= 16320 and |q| < 2^15 fit in 16 bits).
+ *   recon_u8    optional 8-bit plane, recon_pitch bytes per row.
+ * Planes up to 2^22 blocks.  No allocation.
+ * Errors: INVALID_ARG, UNSUPPORTED (size), HIP.
+ */
+rdct_status_t rdct_codec_encode(const uint8_t* src, int32_t width, int32_t height,
+                                int64_t src_pitch, const rdct_select_t* sel, uint16_t* counts,
+                                uint32_t* group_pairs, int32_t* slots, uint8_t* recon_u8,
+                                int64_t recon_pitch, void* stream);
+
+/*
+ * Concatenate the groups written by rdct_codec_encode into one stream:
+ * offsets[b] = index in `packed` of block b's first pair (nblocks + 1 entries,
+ * offsets[nblocks] = total), packed = all pairs in block order.  Pairs at
+ * index >= capacity are not written (compare offsets[nblocks] with capacity;
+ * 64 pairs per block always suffice).  workspace: rdct_codec_groups uint32.
+ * No allocation.  Errors: INVALID_ARG, UNSUPPORTED (size), HIP.
+ */
+rdct_status_t rdct_codec_pack(const uint16_t* counts, const uint32_t* group_pairs,
+                              const int32_t* slots, int32_t width, int32_t height,
+                              uint32_t* offsets, int32_t* packed, int64_t capacity,
+                              uint32_t* workspace, void* stream);
+
+/* ------------------------------------------------------------------------- */
 /* Comparison transforms and image-quality metrics (Sections 2-4)             */
 /* ------------------------------------------------------------------------- */
 

@@ -14,8 +14,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdct.so")
 ARCH = "gfx950"
 
-SOURCES = ["rdct_kernels.hip", "rdct_quality.hip", "rdct_api.cpp", "rdct_batch.cpp", "rdct_server.cpp",
-           "rdct_tune.cpp", "rdct_transforms.cpp", "rdct_quality_api.cpp"]
+SOURCES = ["rdct_kernels.hip", "rdct_quality.hip", "rdct_codec.hip", "rdct_api.cpp",
+           "rdct_batch.cpp", "rdct_server.cpp", "rdct_tune.cpp", "rdct_transforms.cpp",
+           "rdct_quality_api.cpp", "rdct_codec_api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code; the compiler still
 # uses ordinary scalar and 16-bit packed integer instructions.

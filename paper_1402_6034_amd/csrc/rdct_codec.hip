@@ -1,0 +1,253 @@
+// Codec output of the keep-r and quantisation paths (Section 3 keeps the r
+// initial zig-zag coefficients of every block; a codec stores exactly those and
+// shows 8-bit pixels).
+//
+// Encode: one block per lane, 64 blocks (a group) per wave.  Each lane
+// transforms its block (22-addition flow graphs), selects (keep r, or the
+// exact quantiser), codes the kept coefficients in zig-zag order as
+// (run, value) pairs -- a count pass, a wave prefix sum, an emit pass into the
+// wave's LDS area at the lane's offset -- and the wave copies the group's
+// pairs contiguously into the group's slot.  The lane then inverts its block
+// and writes clamp(round(A'), 0, 255).  Pack: one workgroup scans the group
+// totals; every group then writes its block offsets and copies its pairs into
+// the packed stream.
+#include "rdct_device.h"
+
+namespace rdct {
+
+constexpr int kGroup = 64;                 // blocks per group (one wave)
+constexpr int kSlot = kGroup * 64;         // pairs a group can hold
+
+using CodecOut = CodecOutArgs;
+
+struct CodecKArgs {
+  Plane P;
+  CodecOut out;
+  QuantConsts qc;
+};
+
+__device__ __forceinline__ QCPtr codec_table() {
+  const RDCT_CONST char* seg = (const RDCT_CONST char*)__builtin_amdgcn_kernarg_segment_ptr();
+  return (QCPtr)(seg + offsetof(CodecKArgs, qc));
+}
+
+// Pair word: run in the high 16 bits, the value as int16 in the low 16 bits.
+__device__ __forceinline__ int32_t pair_word(int run, int v) {
+  return (int32_t)(((uint32_t)run << 16) | ((uint32_t)v & 0xffffu));
+}
+
+// Round half away from zero and clamp to 0..255.
+__device__ __forceinline__ uint32_t to_u8(double a) {
+  const double r = __builtin_copysign(__builtin_floor(__builtin_fabs(a) + 0.5), a);
+  return (uint32_t)__builtin_fmin(__builtin_fmax(r, 0.0), 255.0);
+}
+
+// Store one reconstructed 8-pixel row (bytes b[0..7]), clipped to the plane.
+__device__ __forceinline__ void store_u8_row(const Plane& P, const CodecOut& o, int x0, int y,
+                                             const uint32_t (&b)[8], bool al8) {
+  if (y >= P.height) return;
+  uint8_t* row = o.recon + (int64_t)y * o.rpitch + x0;
+  if (al8 && x0 + 8 <= P.width) {
+    const uint32_t lo = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+    const uint32_t hi = b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24);
+    *reinterpret_cast<RDCT_GLOBAL u32x2*>(gptr(row)) = (u32x2){lo, hi};
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (x0 + j < P.width) row[j] = (uint8_t)b[j];
+  }
+}
+
+template <int SEL>
+__global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts /*qc*/) {
+  extern __shared__ int32_t lds_pairs[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int group = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int t0 = group * kGroup;
+  if (t0 >= P.nblocks) return;
+  const int t = t0 + lane;
+  const bool valid = t < P.nblocks;
+  int32_t* wpairs = lds_pairs + wave * kSlot;
+
+  uint32_t px[16];
+  int x0, y0;
+  load_block(P, t, valid, px, x0, y0);
+  int v[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[i][j] = pixel(px, i, j) - (SEL == SEL_Q ? P.shift : 0);
+  pass2d<int, true>(v);
+
+  // Selection: keep the first r zig-zag positions, or quantise all 64.
+  const int n_kept = SEL == SEL_Q ? 64 : P.r;
+  if constexpr (SEL == SEL_Q) {
+    const QCPtr qc = codec_table();
+    static_for<0, 64>([&](auto c) {
+      constexpr int kl = decltype(c)::value;
+      v[kl >> 3][kl & 7] = quantize<kl>(v[kl >> 3][kl & 7], qc->qm[kl]);
+    });
+  }
+
+  // Count pass, wave prefix, emit pass.
+  int cnt = 0;
+#pragma unroll
+  for (int rank = 0; rank < 64; ++rank) {
+    const int kl = kZigZag.order[rank];
+    cnt += (rank < n_kept && v[kl >> 3][kl & 7] != 0) ? 1 : 0;
+  }
+  if (!valid) cnt = 0;
+  int off = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(off, d, 64);
+    if (lane >= d) off += u;
+  }
+  const int total = __shfl(off, 63, 64);
+  off -= cnt;                                  // exclusive
+  if (valid) {
+    int run = 0, k = off;
+#pragma unroll
+    for (int rank = 0; rank < 64; ++rank) {
+      const int kl = kZigZag.order[rank];
+      const int val = v[kl >> 3][kl & 7];
+      if (rank < n_kept) {
+        if (val != 0) {
+          wpairs[k++] = pair_word(run, val);
+          run = 0;
+        } else {
+          ++run;
+        }
+      }
+    }
+    o.counts[t] = (uint16_t)cnt;
+  }
+  wave_sync();
+  int32_t* slot = o.slots + (int64_t)group * kSlot;
+  for (int i = lane; i < total; i += 64) slot[i] = wpairs[i];
+  if (lane == 0) o.group_pairs[group] = (uint32_t)total;
+
+  // 8-bit reconstruction.
+  if (o.recon == nullptr || !valid) return;
+  const bool al8 = ((reinterpret_cast<uintptr_t>(o.recon) | (uintptr_t)o.rpitch) & 7u) == 0;
+  if constexpr (SEL == SEL_Q) {
+    const QCPtr qc = codec_table();
+    double w[8][8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int l = 0; l < 8; ++l) w[k][l] = (double)v[k][l] * qc->dq[k * 8 + l];
+    pass2d<double, false>(w);
+    const double sh = (double)P.shift;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      uint32_t b[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[j] = to_u8(w[i][j] + sh);
+      store_u8_row(P, o, x0, y0 + i, b, al8);
+    }
+  } else {
+    // R = C0^T D' (M . Y) D' C0 exactly; pixel = clamp(floor((R + 288) / 576), 0, 255).
+    const uint64_t keep = P.keep;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        v[k][l] = ((keep >> (k * 8 + l)) & 1) ? v[k][l] * (kDp[k] * kDp[l]) : 0;
+    pass2d<int, false>(v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      uint32_t b[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int rr = v[i][j] + 288;
+        b[j] = rr <= 0 ? 0u : min(255u, (uint32_t)rr / 576u);
+      }
+      store_u8_row(P, o, x0, y0 + i, b, al8);
+    }
+  }
+}
+
+// Exclusive scan of the group totals (one workgroup of 1024 threads), total in
+// offsets[nblocks].
+__global__ __launch_bounds__(1024) void k_codec_scan(const uint32_t* __restrict__ group_pairs,
+                                                      int32_t n_groups, uint32_t* __restrict__ base,
+                                                      uint32_t* __restrict__ offsets,
+                                                      int32_t nblocks) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (n_groups + 1023) / 1024;
+  const int g0 = t * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (g0 + i < n_groups) s += group_pairs[g0 + i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint32_t u = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += u;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;   // exclusive prefix of this thread's range
+  for (int i = 0; i < per; ++i)
+    if (g0 + i < n_groups) {
+      base[g0 + i] = run;
+      run += group_pairs[g0 + i];
+    }
+  if (t == 1023) offsets[nblocks] = part[1023];
+}
+
+// One wave per group: block offsets and the copy of the group's pairs.
+__global__ __launch_bounds__(64) void k_codec_pack(const uint16_t* __restrict__ counts,
+                                                   const uint32_t* __restrict__ group_pairs,
+                                                   const int32_t* __restrict__ slots,
+                                                   const uint32_t* __restrict__ base,
+                                                   int32_t nblocks, uint32_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ packed, int64_t capacity) {
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const int t = g * kGroup + lane;
+  const int c = t < nblocks ? (int)counts[t] : 0;
+  int off = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(off, d, 64);
+    if (lane >= d) off += u;
+  }
+  const uint32_t b = base[g];
+  if (t < nblocks) offsets[t] = b + (uint32_t)(off - c);
+  const uint32_t n = group_pairs[g];
+  const int32_t* src = slots + (int64_t)g * kSlot;
+  for (uint32_t i = lane; i < n; i += 64)
+    if ((int64_t)b + i < capacity) packed[b + i] = src[i];
+}
+
+hipError_t launch_codec_encode(int sel, const Plane& P, const CodecOut& o, const QuantConsts& qc,
+                               hipStream_t s) {
+  const int groups = (P.nblocks + kGroup - 1) / kGroup;
+  if (groups <= 0) return hipSuccess;
+  const int wpg = 2;   // 16 KB of LDS per wave
+  const dim3 grid((groups + wpg - 1) / wpg), block(64 * wpg);
+  const size_t lds = (size_t)wpg * kSlot * sizeof(int32_t);
+  if (sel == SEL_Q)
+    hipLaunchKernelGGL(k_codec<SEL_Q>, grid, block, lds, s, P, o, qc);
+  else
+    hipLaunchKernelGGL(k_codec<SEL_ZZ>, grid, block, lds, s, P, o, qc);
+  return hipGetLastError();
+}
+
+hipError_t launch_codec_pack(const uint16_t* counts, const uint32_t* group_pairs,
+                             const int32_t* slots, int32_t nblocks, uint32_t* offsets,
+                             int32_t* packed, int64_t capacity, uint32_t* workspace,
+                             hipStream_t s) {
+  const int groups = (nblocks + kGroup - 1) / kGroup;
+  if (groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codec_scan, dim3(1), dim3(1024), 0, s, group_pairs, groups, workspace,
+                     offsets, nblocks);
+  hipLaunchKernelGGL(k_codec_pack, dim3(groups), dim3(64), 0, s, counts, group_pairs, slots,
+                     workspace, nblocks, offsets, packed, capacity);
+  return hipGetLastError();
+}
+
+}  // namespace rdct

@@ -73,6 +73,21 @@ hipError_t launch_quality(const QPlane& P, const QualityArgs& A, hipStream_t str
 hipError_t launch_quality_batch(const QPlane* planes, const QTile* tiles, int32_t n_tiles,
                                 const QualityArgs& A, hipStream_t stream);
 
+// Codec output (zig-zag run-length pairs and 8-bit reconstruction).
+struct CodecOutArgs {
+  uint16_t* counts;       // pairs per block
+  uint32_t* group_pairs;  // pairs per 64-block group
+  int32_t* slots;         // 4096 pairs per group
+  uint8_t* recon;         // nullable
+  int64_t rpitch;         // bytes per reconstruction row
+};
+hipError_t launch_codec_encode(int sel, const Plane& P, const CodecOutArgs& o,
+                               const QuantConsts& qc, hipStream_t stream);
+hipError_t launch_codec_pack(const uint16_t* counts, const uint32_t* group_pairs,
+                             const int32_t* slots, int32_t nblocks, uint32_t* offsets,
+                             int32_t* packed, int64_t capacity, uint32_t* workspace,
+                             hipStream_t stream);
+
 enum SelKind { SEL_ZZ = 0, SEL_Q = 1 };
 enum CoefKind { CO_NONE = 0, CO_I32 = 1, CO_I16 = 2, CO_F32 = 3 };
 // EV_SPATIAL: squared error from the reconstruction, pixel by pixel.

@@ -122,6 +122,13 @@ def _declare_extra(L):
     L.rdct_batch_autotune.restype = c_int32
     L.rdct_batch_plan_destroy.argtypes = [P]
     L.rdct_batch_plan_destroy.restype = None
+    L.rdct_codec_groups.argtypes = [c_int32, c_int32]
+    L.rdct_codec_groups.restype = c_int64
+    L.rdct_codec_encode.argtypes = [P, c_int32, c_int32, c_int64, POINTER(Select), P, P, P, P,
+                                    c_int64, P]
+    L.rdct_codec_encode.restype = c_int32
+    L.rdct_codec_pack.argtypes = [P, P, P, c_int32, c_int32, P, P, c_int64, P, P]
+    L.rdct_codec_pack.restype = c_int32
     L.rdct_quality_sweep.argtypes = [P, c_int32, c_int32, c_int64, c_int32, c_int32, c_int32, P, P,
                                      P]
     L.rdct_quality_sweep.restype = c_int32
@@ -446,3 +453,56 @@ class QualityPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Codec output (rdct_codec_*)
+# ---------------------------------------------------------------------------
+
+def rdct_codec_groups(width, height):
+    return lib().rdct_codec_groups(width, height)
+
+
+class Codec:
+    """Device buffers for the codec output of planes of one size: per-block
+    pair counts, per-group slots, the packed stream with block offsets, and the
+    8-bit reconstruction."""
+
+    def __init__(self, height, width, device="cuda"):
+        self.h, self.w = height, width
+        self.nb = rdct_num_blocks(width, height)
+        self.groups = rdct_codec_groups(width, height)
+        self.counts = torch.empty(self.nb, dtype=torch.int16, device=device)
+        self.group_pairs = torch.empty(self.groups, dtype=torch.int32, device=device)
+        self.slots = torch.empty(self.groups * 4096, dtype=torch.int32, device=device)
+        self.offsets = torch.empty(self.nb + 1, dtype=torch.int32, device=device)
+        self.packed = torch.empty(self.nb * 64, dtype=torch.int32, device=device)
+        self.workspace = torch.empty(self.groups, dtype=torch.int32, device=device)
+        self.recon = torch.empty((height, width), dtype=torch.uint8, device=device)
+
+    def encode(self, img, sel, recon=True, stream=None):
+        w, h, pitch = _plane_args(img)
+        if (h, w) != (self.h, self.w):
+            raise ValueError("plane size differs from the codec's")
+        _check(lib().rdct_codec_encode(_ptr(img), w, h, pitch, ctypes.byref(sel), _ptr(self.counts),
+                                       _ptr(self.group_pairs), _ptr(self.slots),
+                                       _ptr(self.recon) if recon else None,
+                                       self.recon.stride(0) if recon else 0, _stream(stream)),
+               "rdct_codec_encode")
+
+    def pack(self, stream=None):
+        _check(lib().rdct_codec_pack(_ptr(self.counts), _ptr(self.group_pairs), _ptr(self.slots),
+                                     self.w, self.h, _ptr(self.offsets), _ptr(self.packed),
+                                     self.packed.numel(), _ptr(self.workspace), _stream(stream)),
+               "rdct_codec_pack")
+
+    def pairs_host(self):
+        """Per-block lists of (run, value) from the packed stream."""
+        import numpy as np
+        torch.cuda.synchronize()
+        off = self.offsets.cpu().numpy().astype(np.int64)
+        words = self.packed[:int(off[-1])].cpu().numpy().astype(np.int64) & 0xffffffff
+        runs = words >> 16
+        vals = ((words & 0xffff) ^ 0x8000) - 0x8000
+        return [list(zip(runs[off[b]:off[b + 1]].tolist(), vals[off[b]:off[b + 1]].tolist()))
+                for b in range(self.nb)]

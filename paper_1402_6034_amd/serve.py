@@ -8,6 +8,7 @@ returns per-request latencies.
 from __future__ import annotations
 
 import ctypes
+import gc
 import threading
 import time
 from ctypes import POINTER, c_double, c_int32, c_int64, c_uint8, c_uint64, c_void_p
@@ -133,7 +134,7 @@ def replay(server, trace, planes_of, sel_of, timeout_s=120.0, speed=1.0):
     done = {}
     busy = [0]
     err = []
-    t_start = time.perf_counter()
+    t_start = 0.0
 
     def submitter():
         try:
@@ -157,19 +158,31 @@ def replay(server, trace, planes_of, sel_of, timeout_s=120.0, speed=1.0):
         except Exception as e:  # pragma: no cover
             err.append(e)
 
+    # The cyclic garbage collector is paused for the replay: its pauses (tens of
+    # milliseconds with many live objects) would otherwise show up as request
+    # latency on whichever requests are in flight.
+    gc.collect()
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
+    t_start = time.perf_counter()
     th = threading.Thread(target=submitter, daemon=True)
     th.start()
-    deadline = time.perf_counter() + timeout_s
-    while len(done) < len(trace):
-        for c in server.poll(256, wait_us=2000):
-            # Latency from the request's arrival time to its collection here.
-            c["latency_ms"] = (time.perf_counter() - t_start - trace[c["tag"]].arrival_s / speed) * 1e3
-            done[c["tag"]] = c
-        if err:
-            raise err[0]
-        if time.perf_counter() > deadline:
-            raise TimeoutError(f"replay: {len(done)} of {len(trace)} completed")
-    th.join()
+    try:
+        deadline = time.perf_counter() + timeout_s
+        while len(done) < len(trace):
+            for c in server.poll(256, wait_us=2000):
+                # Latency from the request's arrival time to its collection here.
+                c["latency_ms"] = (time.perf_counter() - t_start
+                                   - trace[c["tag"]].arrival_s / speed) * 1e3
+                done[c["tag"]] = c
+            if err:
+                raise err[0]
+            if time.perf_counter() > deadline:
+                raise TimeoutError(f"replay: {len(done)} of {len(trace)} completed")
+        th.join()
+    finally:
+        if gc_was_enabled:
+            gc.enable()
     return done, time.perf_counter() - t_start, busy[0]
 
 

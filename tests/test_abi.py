@@ -174,3 +174,23 @@ def test_quality_sweep_rejects():
     assert L.rdct_quality_plan_create(d, 2, R.T_RDCT_FLOOR, 1, 45, FAKE_SSE, FAKE_DST, ctypes.byref(h)) == R.ERR_UNSUPPORTED
     assert L.rdct_quality_plan_create(d, 0, R.T_DCT, 1, 45, FAKE_SSE, FAKE_DST, ctypes.byref(h)) == R.ERR_INVALID_ARG
     assert L.rdct_quality_plan_run(None, None) == R.ERR_INVALID_ARG
+
+
+@needs_no_gpu
+def test_codec_rejects():
+    L = R.lib()
+    z = R.select(R.SEL_ZIGZAG, r=10)
+
+    def enc(sel=z, w=64, h=64, counts=FAKE_DST, gp=FAKE_DST, slots=FAKE_DST, recon=None, rp=0):
+        return L.rdct_codec_encode(FAKE_SRC, w, h, w, ctypes.byref(sel), counts, gp, slots, recon,
+                                   rp, None)
+    assert enc(sel=R.select(R.SEL_ZIGZAG, r=0)) == R.ERR_INVALID_ARG
+    assert enc(counts=None) == R.ERR_INVALID_ARG
+    assert enc(slots=FAKE_DST + 2) == R.ERR_INVALID_ARG
+    assert enc(recon=FAKE_DST, rp=10) == R.ERR_INVALID_ARG
+    assert enc(w=20000, h=16400) == R.ERR_UNSUPPORTED        # above 2^22 blocks
+    assert L.rdct_codec_pack(FAKE_DST, FAKE_DST, FAKE_DST, 64, 64, None, FAKE_DST, 10, FAKE_DST,
+                             None) == R.ERR_INVALID_ARG
+    assert L.rdct_codec_pack(FAKE_DST, FAKE_DST, FAKE_DST, 64, 64, FAKE_DST, None, 10, FAKE_DST,
+                             None) == R.ERR_INVALID_ARG
+    assert R.rdct_codec_groups(64, 64) == 1 and R.rdct_codec_groups(72, 64) == 2
