@@ -9,7 +9,7 @@
  * S = sqrt((C0 C0^T)^-1) = diag(1/sqrt(g)), g = (8,6,4,6,8,6,4,6)) is never
  * applied to pixels: it is folded into the step that follows the transform,
  * either the retention of the first r zig-zag coefficients (Section 3) or a
- * quantisation table (Section 2, "merged into the quantization step").  The
+ * quantisation table (Section 2 folds S into the quantisation).  The
  * inverse runs through the transpose, since C_orth = S C0 is orthogonal
  * (Section 2), and the result is scored by SSE / MSE / PSNR (Section 3).
  *
@@ -98,7 +98,7 @@ rdct_status_t rdct_forward(const uint8_t* src, int32_t width, int32_t height,
                            void* coef, rdct_coef_t coef_type, void* stream);
 
 /*
- * Inverse transform (Section 3 "inverse procedure"; C_orth^-1 = C_orth^T,
+ * Inverse transform (Section 3 inverts the kept coefficients; C_orth^-1 = C_orth^T,
  * Section 2) of block-major coefficients back to a float plane.
  *   coef_type I32/I16 with NONE or ZIGZAG: integer Y, positions of rank >= r
  *     ignored; A' = C0^T D' Y D' C0 / 576 (D' = diag(24/g)), exact integer

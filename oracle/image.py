@@ -3,7 +3,7 @@
 Test infrastructure only (see the package docstring).
 
 Section 3 divides each image into 8x8 sub-blocks, transforms each block, keeps
-the r initial zig-zag coefficients, applies the inverse procedure and measures
+the r initial zig-zag coefficients, inverts the transform and measures
 PSNR.  Readings where the paper is silent: planes whose sides are not multiples
 of 8 are padded by replicating the last row and column, and every metric is
 taken over the plane's own pixels only.  Coefficients are laid out block-major:

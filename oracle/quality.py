@@ -7,7 +7,7 @@ transforms: the average PSNR, and the average UQI and MSE given as absolute
 percentage errors (APE) relative to the exact DCT.  Section 2 introduces the
 signed DCT (SDCT) as the main comparator, and Section 4 suggests floor and
 ceiling in place of the round-off.  Every transform here is an 8x8 matrix T
-applied to each block as T A T^T (Section 3); the inverse procedure is
+applied to each block as T A T^T (Section 3); the inverse is
 A' = T^-1 (M_r . Y) T^-T, which is T^T (M_r . Y) T for the orthogonal ones.
 
 Transforms:

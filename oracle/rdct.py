@@ -199,7 +199,7 @@ def retention_mask(r: int) -> np.ndarray:
     return (zigzag_rank() < r).astype(np.int64)
 
 
-# --- quantisation (S merged into the quantisation step, Section 2) ----------
+# --- quantisation (S folded into the quantisation, Section 2) ----------------
 
 # JPEG luminance quant table for quality 50 (ITU-T T.81 Annex K, Table K.1),
 # natural order, row index = vertical frequency k.
@@ -245,7 +245,7 @@ def quantize(y: np.ndarray, qtab: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Inverse (Section 3: inverse procedure; C_orth^-1 = C_orth^T, Section 2)
+# Inverse (Section 3 inverts the kept coefficients; C_orth^-1 = C_orth^T, Section 2)
 # ---------------------------------------------------------------------------
 
 

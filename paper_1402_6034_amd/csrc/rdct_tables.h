@@ -6,8 +6,9 @@
 // here: it is folded into the retention / quantisation step (Section 2).
 //
 // Natural coefficient order: index k * 8 + l with k the vertical and l the
-// horizontal frequency.  Zig-zag order: the JPEG sequence (Section 3 "standard
-// zigzag sequence"), generated here by walking the block with bounces.
+// horizontal frequency.  Zig-zag order: the JPEG scan (Section 3 keeps the
+// coefficients in the usual zig-zag order), generated here by walking the block
+// with bounces.
 #pragma once
 #include <stdint.h>
 
