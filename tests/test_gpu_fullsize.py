@@ -1,0 +1,132 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configurations
+bench.py times: sampled blocks against the oracle, block by block, and
+size-independent properties (batch == single plane, sums over blocks).
+
+  * frame   8192 x 8192, quality 50, int16 q (single-plane kernel)
+  * ragged  the 1000-plane batch (persistent kernel, default geometry and the
+            autotuned one), int16 q + float32 reconstruction + per-plane SSE
+  * sweep   256 planes of 512 x 512, keep r = 1..45 (one launch per plane)
+  * codec   the 8192 x 8192 frame through encode + pack
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1402_6034_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+R = pytest.importorskip("paper_1402_6034_amd.rdct")
+DEV = "cuda:0"
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def sample_idx(rng, nb, k):
+    idx = np.unique(np.concatenate([[0, nb - 1], rng.integers(0, nb, size=k)]))
+    return idx
+
+
+@pytest.fixture(scope="module")
+def frame():
+    img = synth.render(0, 8192, 8192, device=DEV)
+    return img, host(img)
+
+
+def oracle_q_blocks(img_np, idx, quality, shift=128):
+    blocks = O.sample_blocks(img_np, idx)
+    y = O.forward_blocks(blocks, shift)
+    return O.quantize(y, O.quant_table(quality)), y
+
+
+def test_frame_quantise_sampled(frame):
+    img, img_np = frame
+    sel = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+    q = R.forward(img, sel, R.COEF_I16)
+    nb = 1024 * 1024
+    idx = sample_idx(np.random.default_rng(0), nb, 3000)
+    want, _ = oracle_q_blocks(img_np, idx, 50)
+    got = host(q[torch.from_numpy(idx).to(DEV)]).astype(np.int64)
+    assert np.array_equal(got, want.reshape(-1, 64))
+
+
+def test_codec_frame_sampled(frame):
+    img, img_np = frame
+    c = R.Codec(8192, 8192, DEV)
+    c.encode(img, R.select(R.SEL_QUANT, quality=50, level_shift=128))
+    c.pack()
+    torch.cuda.synchronize()
+    nb = 1024 * 1024
+    counts = host(c.counts).astype(np.int64) & 0xffff
+    off = host(c.offsets).astype(np.int64)
+    assert off[0] == 0 and np.array_equal(np.diff(off), counts)
+    idx = sample_idx(np.random.default_rng(1), nb, 1500)
+    q, _ = oracle_q_blocks(img_np, idx, 50)
+    words = host(c.packed).astype(np.int64) & 0xffffffff
+    recon = host(c.recon)
+    qt = O.quant_table(50)
+    for n, b in enumerate(idx):
+        pairs = O.rle_encode(O.zigzag_scan(q[n], 64))
+        w = words[off[b]:off[b + 1]]
+        assert list(zip((w >> 16).tolist(), (((w & 0xffff) ^ 0x8000) - 0x8000).tolist())) == pairs
+        rec = O.inverse_orth(O.dequantize(q[n], qt)) + 128
+        by, bx = divmod(int(b), 1024)
+        got = recon[by * 8:by * 8 + 8, bx * 8:bx * 8 + 8]
+        near = np.abs(np.abs(rec - np.floor(rec)) - 0.5) < 1e-9
+        assert np.array_equal(got[~near], O.u8_from_float(rec)[~near])
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    items = synth.ragged_batch(0, 1000)
+    imgs = [synth.render(it.seed, it.height, it.width, device=DEV) for it in items]
+    sels = [R.select(R.SEL_QUANT, quality=it.quality, level_shift=128) for it in items]
+    return items, imgs, sels
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_ragged_batch_sampled(ragged, autotune, tmp_path, monkeypatch):
+    monkeypatch.setenv("RDCT_TUNING_CACHE", str(tmp_path / "tune.json"))
+    items, imgs, sels = ragged
+    plan = R.BatchPlan(imgs, sels, R.COEF_I16, recon=True)
+    if autotune:
+        plan.autotune(reps=2)
+    plan.run()
+    sse = host(plan.sse)
+    rng = np.random.default_rng(2)
+    order = np.argsort([it.height * it.width for it in items])
+    for i in list(order[:40]) + list(rng.choice(1000, size=40, replace=False)):
+        it, img_np = items[i], host(imgs[i])
+        h, w = img_np.shape
+        nb = (h // 8) * (w // 8)
+        idx = sample_idx(rng, nb, 16)
+        want_q, _ = oracle_q_blocks(img_np, idx, it.quality)
+        got_q = host(plan.coef_views[i][torch.from_numpy(idx).to(DEV)]).astype(np.int64)
+        assert np.array_equal(got_q, want_q.reshape(-1, 64)), i
+        rec = host(plan.recon_views[i])
+        qt = O.quant_table(it.quality)
+        for n, b in enumerate(idx):
+            want = O.inverse_orth(O.dequantize(want_q[n], qt)) + 128
+            by, bx = divmod(int(b), w // 8)
+            assert np.max(np.abs(rec[by * 8:by * 8 + 8, bx * 8:bx * 8 + 8] - want)) <= 1e-4, i
+        if h * w <= 256 * 256:
+            ref = O.quant_eval(img_np, qt)
+            assert abs(int(sse[i]) * 2.0 ** -20 - ref["sse"]) <= nb * 2.0 ** -21 + 1e-9 * ref["sse"], i
+    # Property at any size: the batch gives every plane the bits it gets alone.
+    for i in rng.choice(1000, size=12, replace=False):
+        s1, _, _ = R.compress_eval(imgs[i], sels[i], 1)
+        assert int(host(s1)[0]) == int(sse[i]), i
+    plan.close()
+
+
+def test_sweep_planes_full():
+    sel = R.select(R.SEL_ZIGZAG, r=1)
+    for s in (0, 17, 255):
+        img = synth.render(s, 512, 512, device=DEV)
+        sse, _, _ = R.compress_eval(img, sel, 45)
+        ref = O.retention_eval(host(img), range(1, 46))
+        assert [int(v) for v in host(sse)] == [ref["sse_num"][r] for r in range(1, 46)]
