@@ -305,12 +305,21 @@ class QualitySweep:
     # transform (2048 per block over 45 values of r) about 1 -> 34.
     flops_per_pixel_r = 34
 
-    def __init__(self, n=256, size=512, r_count=45):
+    def __init__(self, n=256, size=512, r_count=45, planes_cache=None):
+        import numpy as np
+        import torch
         from paper_1402_6034_amd import rdct as R, synth
         self.R = R
         self.n, self.size, self.r_count = n, size, r_count
-        log(f"[bench] rendering {n} planes {size}x{size}")
-        self.imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
+        if planes_cache and os.path.exists(planes_cache):
+            log(f"[bench] loading {n} planes from {planes_cache}")
+            arr = np.load(planes_cache)
+            self.imgs = [torch.from_numpy(arr[s]).cuda() for s in range(n)]
+        else:
+            log(f"[bench] rendering {n} planes {size}x{size}")
+            self.imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
+            if planes_cache:
+                np.save(planes_cache, np.stack([im.cpu().numpy() for im in self.imgs]))
         self.transforms = [R.T_DCT, R.T_RDCT, R.T_SDCT]
         self.plans = [R.QualityPlan(self.imgs, t, 1, r_count) for t in self.transforms]
         self.nb1 = (size // 8) ** 2
@@ -559,7 +568,7 @@ def main():
                     help="requests in the served trace (2000 req/s; 0 = skip the serving leg; "
                          "default 4000 with the ragged workload, else 0)")
     ap.add_argument("--planes-cache", default=None,
-                    help="ragged: .npy file holding the rendered planes (written if absent)")
+                    help="ragged, quality: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -579,6 +588,8 @@ def main():
     torch.cuda.init()
     if args.workload == "ragged":
         wl = RaggedBatch(planes_cache=args.planes_cache, autotune=not args.no_autotune)
+    elif args.workload == "quality":
+        wl = QualitySweep(planes_cache=args.planes_cache)
     else:
         wl = WORKLOADS[args.workload]()
 

@@ -36,10 +36,11 @@ __device__ __forceinline__ int32_t pair_word(int run, int v) {
   return (int32_t)(((uint32_t)run << 16) | ((uint32_t)v & 0xffffu));
 }
 
-// Round half away from zero and clamp to 0..255.
-__device__ __forceinline__ uint32_t to_u8(double a) {
-  const double r = __builtin_copysign(__builtin_floor(__builtin_fabs(a) + 0.5), a);
-  return (uint32_t)__builtin_fmin(__builtin_fmax(r, 0.0), 255.0);
+// clamp(round(v), 0, 255) with halves away from zero, given t = v + 1/2: for
+// v >= 0 the rounding is floor(t) = trunc(t); every v < 0 clamps to 0, and so
+// does trunc(t) for t < 1.
+__device__ __forceinline__ uint32_t to_u8(double t) {
+  return (uint32_t)min(max((int)t, 0), 255);
 }
 
 // Store one reconstructed 8-pixel row (bytes b[0..7]), clipped to the plane.
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
 #pragma unroll
       for (int l = 0; l < 8; ++l) w[k][l] = (double)v[k][l] * qc->dq[k * 8 + l];
     pass2d<double, false>(w);
-    const double sh = (double)P.shift;
+    const double sh = (double)P.shift + 0.5;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       uint32_t b[8];
