@@ -162,46 +162,95 @@ class FrameQuant:
                           "forward + exact quantisation"}
 
 
-class PlainSweep:
-    """256 planes of 512 x 512, seeds 0..255: forward, S-scaled retention swept
-    over r = 1..45, inverse error and per-plane PSNR; one launch per plane."""
-    name = "plain-256x512x512-sweep-r1-45"
-    workload_key = "sweep"
-    dtype = "int16+int64"
+def seeded_planes(n, size, planes_cache=None):
+    """Planes 0..n-1 of size x size from the synthetic generator, on the device.
+    With planes_cache, loaded from (or first written to) that .npy file, so a
+    profiled run issues no rendering kernels."""
+    import numpy as np
+    import torch
+    from paper_1402_6034_amd import synth
+    if planes_cache and os.path.exists(planes_cache):
+        log(f"[bench] loading {n} planes from {planes_cache}")
+        arr = np.load(planes_cache)
+        return [torch.from_numpy(arr[s]).cuda() for s in range(n)]
+    log(f"[bench] rendering {n} planes {size}x{size}")
+    imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
+    if planes_cache:
+        np.save(planes_cache, np.stack([im.cpu().numpy() for im in imgs]))
+    return imgs
 
-    def __init__(self, n=256, size=512):
-        import torch
-        from paper_1402_6034_amd import rdct as R, synth
+
+class RetentionSweep:
+    """256 planes of 512 x 512, seeds 0..255: forward to int32 coefficients and
+    the retention error of every plane for r = 1..45 (exact integer SSE from
+    coefficient energies, then PSNR): one persistent batch launch per step.
+    `plain()` times the same work as one rdct_compress_eval launch per plane."""
+    name = "sweep-256x512x512-r1-45"
+    workload_key = "sweep"
+    dtype = "int32+int64"
+
+    def __init__(self, n=256, size=512, autotune=True, planes_cache=None):
+        from paper_1402_6034_amd import rdct as R
         self.R = R
         self.n, self.size = n, size
-        log(f"[bench] rendering {n} planes {size}x{size}")
-        self.imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
-        self.sse = torch.empty((n, 45), dtype=torch.int64, device="cuda")
+        self.imgs = seeded_planes(n, size, planes_cache)
         self.sel = R.select(R.SEL_ZIGZAG, r=1)
+        self.plan = R.BatchPlan(self.imgs, [self.sel] * n, R.COEF_I32, recon=False, r_count=45)
+        if autotune:
+            t = self.plan.autotune(reps=5)
+            log(f"[bench] autotuned: waves/wg {t.waves_per_wg}, wg/cu {t.wgs_per_cu}")
         self.nb1 = (size // 8) ** 2
         self.psnr = None
 
     def launch(self, i=0):
-        k = i % self.n
-        self.R.compress_eval(self.imgs[k], self.sel, 45, sse=self.sse[k])
+        self.plan.run()
 
     kernel_launch = launch
 
     def step(self):
         import numpy as np
-        for k in range(self.n):
-            self.R.compress_eval(self.imgs[k], self.sel, 45, sse=self.sse[k])
-        s = self.sse.cpu().numpy().astype(np.float64) / 576.0 ** 2
+        self.plan.run()
+        s = self.plan.sse.cpu().numpy().astype(np.float64) / 576.0 ** 2
         mse = s / float(self.size * self.size)
         with np.errstate(divide="ignore"):
             self.psnr = 10.0 * np.log10(255.0 ** 2 / mse)
 
     blocks_per_step = property(lambda self: self.n * self.nb1)
-    bytes_per_block = 64
+    bytes_per_block = 64 + 256
 
     def config(self):
+        t = self.plan.tuning
         return {"workload": self.name, "planes": self.n, "plane": [self.size, self.size],
-                "r": [1, 45], "launches_per_step": self.n}
+                "r": [1, 45], "coef": "int32", "launches_per_step": 1, "waves_per_wg": t.waves_per_wg,
+                "wgs_per_cu": t.wgs_per_cu, "graph": bool(t.use_graph)}
+
+    def plain(self, steps=3):
+        """The same sweep as one rdct_compress_eval launch per plane."""
+        import torch
+        R = self.R
+        sse = torch.empty((self.n, 45), dtype=torch.int64, device="cuda")
+        coef = torch.empty((self.n, self.nb1, 64), dtype=torch.int32, device="cuda")
+
+        def one(k):
+            R.compress_eval(self.imgs[k], self.sel, 45, R.COEF_I32, sse=sse[k], coef=coef[k])
+
+        def once():
+            for k in range(self.n):
+                one(k)
+            sse.cpu()
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            once()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        k_ms = event_time_ms(lambda i: one(i % self.n), 64)
+        same = bool(torch.equal(sse, self.plan.sse)) and bool(torch.equal(coef.view(-1),
+                                                                           self.plan.coef))
+        return {"value": round(self.blocks_per_step / (ms * 1e-3) / 1e6, 3), "unit": "Mblocks/s",
+                "ms_per_step": round(ms, 4), "launches_per_step": self.n,
+                "kernel_ms_per_plane": round(k_ms, 5), "identical_output": same}
 
     def cpu_baseline(self, budget_s):
         import oracle as O
@@ -306,20 +355,10 @@ class QualitySweep:
     flops_per_pixel_r = 34
 
     def __init__(self, n=256, size=512, r_count=45, planes_cache=None):
-        import numpy as np
-        import torch
-        from paper_1402_6034_amd import rdct as R, synth
+        from paper_1402_6034_amd import rdct as R
         self.R = R
         self.n, self.size, self.r_count = n, size, r_count
-        if planes_cache and os.path.exists(planes_cache):
-            log(f"[bench] loading {n} planes from {planes_cache}")
-            arr = np.load(planes_cache)
-            self.imgs = [torch.from_numpy(arr[s]).cuda() for s in range(n)]
-        else:
-            log(f"[bench] rendering {n} planes {size}x{size}")
-            self.imgs = [synth.render(s, size, size, device="cuda") for s in range(n)]
-            if planes_cache:
-                np.save(planes_cache, np.stack([im.cpu().numpy() for im in self.imgs]))
+        self.imgs = seeded_planes(n, size, planes_cache)
         self.transforms = [R.T_DCT, R.T_RDCT, R.T_SDCT]
         self.plans = [R.QualityPlan(self.imgs, t, 1, r_count) for t in self.transforms]
         self.nb1 = (size // 8) ** 2
@@ -545,7 +584,7 @@ def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
     return out
 
 
-WORKLOADS = {"frame": FrameQuant, "sweep": PlainSweep, "ragged": RaggedBatch,
+WORKLOADS = {"frame": FrameQuant, "sweep": RetentionSweep, "ragged": RaggedBatch,
              "quality": QualitySweep, "codec": CodecFrame}
 
 
@@ -563,12 +602,12 @@ def main():
     ap.add_argument("--workload", default="ragged", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="ragged: use the tuning cache (or defaults) instead of tuning first")
+                    help="ragged, sweep: use the tuning cache (or defaults) instead of tuning first")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests in the served trace (2000 req/s; 0 = skip the serving leg; "
                          "default 4000 with the ragged workload, else 0)")
     ap.add_argument("--planes-cache", default=None,
-                    help="ragged, quality: .npy file holding the rendered planes (written if absent)")
+                    help="ragged, sweep, quality: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -588,6 +627,8 @@ def main():
     torch.cuda.init()
     if args.workload == "ragged":
         wl = RaggedBatch(planes_cache=args.planes_cache, autotune=not args.no_autotune)
+    elif args.workload == "sweep":
+        wl = RetentionSweep(autotune=not args.no_autotune, planes_cache=args.planes_cache)
     elif args.workload == "quality":
         wl = QualitySweep(planes_cache=args.planes_cache)
     else:
@@ -620,7 +661,7 @@ def main():
                     "kernel_ms": round(k_ms, 5), "flops_per_launch": flops,
                     "kernel_source_sha256": kernel_source_hash()}
     else:
-        nb = wl.blocks_per_step if not isinstance(wl, PlainSweep) else wl.nb1
+        nb = wl.blocks_per_step
         alg_bytes = int(round(nb * wl.bytes_per_block))
         achieved = alg_bytes / (k_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

@@ -194,8 +194,29 @@ rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
                                      rdct_coef_t coef_type, uint64_t* sse_out,
                                      const rdct_tuning_t* tuning, rdct_batch_plan_t** out);
 
-/* Run the plan on `stream` (asynchronous; no allocation).  With use_graph the
-   first run captures the launch sequence into a hipGraph; later runs replay it. */
+/*
+ * A batched retention sweep (Section 3, keep the r initial zig-zag coefficients,
+ * for a range of r): every plane's sel has mode ZIGZAG and gives the first r,
+ * and each run writes sse_out[i * r_count + j] = the error of plane i at
+ * r = sel.r + j (units of rdct_sse_unit(RDCT_SEL_ZIGZAG)), exactly what
+ * rdct_compress_eval gives for that plane alone with the same r_count.  The
+ * sums come from coefficient energies (Parseval through the exact inverse), so
+ * every plane must consist of whole blocks (width and height multiples of 8);
+ * coefficients and reconstruction (kept at r = sel.r) are optional as in
+ * rdct_batch_plan_create.  sse_out holds n * r_count entries.
+ * Errors: INVALID_ARG (r_count < 1, a mode other than ZIGZAG with r_count > 1,
+ * sel.r + r_count - 1 > 64, or any error of rdct_batch_plan_create),
+ * UNSUPPORTED (a plane with a partial block), NO_MEMORY, HIP.
+ */
+rdct_status_t rdct_batch_plan_create_sweep(const rdct_plane_desc_t* planes, int32_t n,
+                                           int32_t r_count, rdct_coef_t coef_type,
+                                           uint64_t* sse_out, const rdct_tuning_t* tuning,
+                                           rdct_batch_plan_t** out);
+
+/* Run the plan on `stream` (asynchronous; no allocation): a launch that clears
+   sse_out, then the persistent kernel.  With use_graph the first run captures
+   the two launches into a hipGraph; later runs replay it.  Runs of one plan must
+   not overlap (on two streams at once): they share the plan's outputs. */
 rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
 
 /* Blocks and work items of a plan, and the geometry it runs with (any pointer

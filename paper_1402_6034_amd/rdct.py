@@ -114,6 +114,9 @@ def _declare_extra(L):
     L.rdct_batch_plan_create.argtypes = [POINTER(PlaneDesc), c_int32, c_int32, P,
                                          POINTER(Tuning), POINTER(c_void_p)]
     L.rdct_batch_plan_create.restype = c_int32
+    L.rdct_batch_plan_create_sweep.argtypes = [POINTER(PlaneDesc), c_int32, c_int32, c_int32, P,
+                                               POINTER(Tuning), POINTER(c_void_p)]
+    L.rdct_batch_plan_create_sweep.restype = c_int32
     L.rdct_batch_run.argtypes = [P, P]
     L.rdct_batch_run.restype = c_int32
     L.rdct_batch_plan_info.argtypes = [P, POINTER(c_int64), POINTER(c_int32), POINTER(Tuning)]
@@ -276,6 +279,14 @@ def rdct_batch_plan_create(descs, n, coef_type, sse_out, tuning=None):
     return h
 
 
+def rdct_batch_plan_create_sweep(descs, n, r_count, coef_type, sse_out, tuning=None):
+    h = c_void_p()
+    _check(lib().rdct_batch_plan_create_sweep(descs, n, r_count, coef_type, _ptr(sse_out),
+                                              ctypes.byref(tuning) if tuning is not None else None,
+                                              ctypes.byref(h)), "rdct_batch_plan_create_sweep")
+    return h
+
+
 def rdct_batch_run(plan, stream=None):
     _check(lib().rdct_batch_run(plan, _stream(stream)), "rdct_batch_run")
 
@@ -302,9 +313,11 @@ class BatchPlan:
     """A batch of device planes with their selections; outputs are allocated here
     (coefficients and reconstructions as slices of two flat buffers) and stay
     resident.  `run()` launches the whole batch; `sse` holds one raw error sum
-    per plane (see rdct_sse_unit)."""
+    per plane (see rdct_sse_unit), or with r_count > 1 (a retention sweep over
+    r = sel.r .. sel.r + r_count - 1) an (n, r_count) array of them."""
 
-    def __init__(self, planes, sels, coef_type=None, recon=False, tuning=None, device=None):
+    def __init__(self, planes, sels, coef_type=None, recon=False, tuning=None, device=None,
+                 r_count=1):
         if len(planes) != len(sels) or not planes:
             raise ValueError("planes and selections must be non-empty and equal in number")
         dev = planes[0].device if device is None else device
@@ -327,7 +340,8 @@ class BatchPlan:
             for i, (h, w) in enumerate(self.shapes):
                 self.recon_views[i] = self.recon[off:off + h * w].view(h, w)
                 off += h * w
-        self.sse = torch.zeros(self.n, dtype=torch.int64, device=dev)
+        self.r_count = r_count
+        self.sse = torch.zeros(self.n * r_count, dtype=torch.int64, device=dev)
         descs = (PlaneDesc * self.n)()
         for i, (img, sel) in enumerate(zip(self.planes, self.sels)):
             w, h, pitch = _plane_args(img)
@@ -339,7 +353,12 @@ class BatchPlan:
             d.recon_pitch = w if recon else 0
         self._descs = descs
         self.coef_type = COEF_I32 if coef_type is None else coef_type
-        self.handle = rdct_batch_plan_create(descs, self.n, self.coef_type, self.sse, tuning)
+        if r_count == 1:
+            self.handle = rdct_batch_plan_create(descs, self.n, self.coef_type, self.sse, tuning)
+        else:
+            self.handle = rdct_batch_plan_create_sweep(descs, self.n, r_count, self.coef_type,
+                                                       self.sse, tuning)
+            self.sse = self.sse.view(self.n, r_count)
         self.n_blocks, self.n_items, self.tuning = rdct_batch_plan_info(self.handle)
 
     def run(self, stream=None):

@@ -134,6 +134,17 @@ def test_batch_plan_create_rejects():
     assert L.rdct_batch_plan_create(arr, 0, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
     assert L.rdct_batch_run(None, None) == R.ERR_INVALID_ARG
     assert L.rdct_batch_autotune(None, 3, None, None) == R.ERR_INVALID_ARG
+    # Sweeps: zig-zag only, r range within 64, whole blocks, r_count >= 1.
+    sw = L.rdct_batch_plan_create_sweep
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_QUANT))
+    assert sw(arr, 1, 4, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_ZIGZAG))
+    assert sw(arr, 1, 0, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    assert sw(arr, 1, 56, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_ZIGZAG, width=60))
+    assert sw(arr, 1, 4, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    arr = (R.PlaneDesc * 1)(desc(R.SEL_NONE))
+    assert sw(arr, 1, 2, R.COEF_I16, FAKE_SSE, None, ctypes.byref(h)) == R.ERR_INVALID_ARG
 
 
 def test_quality_units_and_windows():

@@ -125,3 +125,35 @@ def test_batch_of_one_full_hd_plane_and_tiny_planes():
     ref = O.retention_eval(imgs[3], [3])
     assert int(sse[3]) == ref["sse_num"][3]
     plan.close()
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_sweep_batch_equals_single_and_oracle(use_graph):
+    imgs, dev, rng = ragged_planes(19, 5)
+    count = 12
+    r0s = [int(r) for r in rng.integers(1, 64 - count + 2, size=len(imgs))]
+    sels = [R.select(R.SEL_ZIGZAG, r=r) for r in r0s]
+    plan = R.BatchPlan(dev, sels, R.COEF_I32, recon=True, r_count=count,
+                       tuning=R.Tuning(2, 4, use_graph, 0))
+    for _ in range(2):          # twice: the sums are cleared by every run
+        plan.run()
+    sse = host(plan.sse)
+    assert sse.shape == (len(imgs), count)
+    for i, (img, d, sel) in enumerate(zip(imgs, dev, sels)):
+        s1, c1, r1 = R.compress_eval(d, sel, count, R.COEF_I32, True)
+        assert np.array_equal(host(s1), sse[i]), i
+        assert np.array_equal(host(c1), host(plan.coef_views[i])), i
+        assert np.array_equal(host(r1), host(plan.recon_views[i])), i
+    for i in (0, 7, 18):
+        rs = list(range(r0s[i], r0s[i] + count))
+        ref = O.retention_eval(imgs[i], rs)
+        assert [int(v) for v in sse[i]] == [ref["sse_num"][r] for r in rs], i
+    plan.close()
+
+
+def test_sweep_batch_rejects_partial_blocks():
+    imgs, dev, _ = ragged_planes(3, 6)
+    dev.append(torch.from_numpy(synth.render_np(7, 20, 24)).to(DEV))
+    sels = [R.select(R.SEL_ZIGZAG, r=1) for _ in dev]
+    with pytest.raises(R.RdctError):
+        R.BatchPlan(dev, sels, None, r_count=45)

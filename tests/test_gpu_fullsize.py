@@ -5,7 +5,8 @@ size-independent properties (batch == single plane, sums over blocks).
   * frame   8192 x 8192, quality 50, int16 q (single-plane kernel)
   * ragged  the 1000-plane batch (persistent kernel, default geometry and the
             autotuned one), int16 q + float32 reconstruction + per-plane SSE
-  * sweep   256 planes of 512 x 512, keep r = 1..45 (one launch per plane)
+  * sweep   256 planes of 512 x 512, keep r = 1..45 (one batch launch, and
+            one launch per plane)
   * codec   the 8192 x 8192 frame through encode + pack
 """
 import numpy as np
@@ -130,3 +131,18 @@ def test_sweep_planes_full():
         sse, _, _ = R.compress_eval(img, sel, 45)
         ref = O.retention_eval(host(img), range(1, 46))
         assert [int(v) for v in host(sse)] == [ref["sse_num"][r] for r in range(1, 46)]
+
+
+def test_sweep_batched_full():
+    imgs = [synth.render(s, 512, 512, device=DEV) for s in range(256)]
+    sel = R.select(R.SEL_ZIGZAG, r=1)
+    plan = R.BatchPlan(imgs, [sel] * 256, None, recon=False, r_count=45)
+    plan.run()
+    sse = host(plan.sse)
+    for s in range(256):
+        s1, _, _ = R.compress_eval(imgs[s], sel, 45)
+        assert np.array_equal(host(s1), sse[s]), s
+    for s in (3, 128):
+        ref = O.retention_eval(host(imgs[s]), range(1, 46))
+        assert [int(v) for v in sse[s]] == [ref["sse_num"][r] for r in range(1, 46)], s
+    plan.close()
