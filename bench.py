@@ -343,7 +343,7 @@ class QualitySweep:
     approximation and the signed DCT, scored per plane by MSE and by the mean
     UQI over 8x8 windows; averaged over planes and given as the APE of each
     approximation relative to the DCT.  One launch per transform (a device list
-    of 32 x 64 window tiles over all planes)."""
+    of 32 x 32 window tiles over all planes)."""
     name = "quality-256x512x512-dct-rdct-sdct-r1-45"
     workload_key = "quality"
     dtype = "f64"

@@ -302,7 +302,7 @@ typedef enum {
  *   sse_out[i]  sum over the plane of (A - A'_r)^2 in units of
  *               rdct_quality_sse_unit(transform): exact for RDCT (1/576^2) and
  *               SDCT (1/64^2); for DCT and RDCT_CEIL float64 sums rounded to
- *               2^-20 per 32 x 64 tile of windows.
+ *               2^-20 per 32 x 32 tile of windows.
  *   uqi_out[i]  sum over the (H - 7)(W - 7) windows of
  *               Q = [2 s_xy / (s_x^2 + s_y^2)] [2 xbar ybar / (xbar^2 + ybar^2)]
  *               (a factor whose denominator is 0 counts as 1; so that float64
@@ -311,8 +311,9 @@ typedef enum {
                window mean of magnitude <= 2^-24 as 0), as int64 in units
  *               of 2^-32 (float64 per tile, then rounded); mean UQI =
  *               uqi_out * 2^-32 / rdct_quality_windows(width, height).  For RDCT and
- *               SDCT the window sums are exact integers, so only the final
- *               division of each window rounds.
+ *               SDCT the window sums are exact integers, so only each window's
+ *               final quotient rounds (its two factors are formed as one
+ *               product over one product, then divided once).
  * The reconstruction is real-valued (no rounding or clipping).  Width and height
  * must be multiples of 8 (else UNSUPPORTED); planes up to 2^20 blocks.  Both
  * outputs are device arrays of r_count entries, overwritten.  No allocation.
@@ -341,7 +342,7 @@ typedef struct rdct_quality_plan rdct_quality_plan_t;
 
 /*
  * Plan over n planes and one transform: every run computes rdct_quality_sweep
- * for each plane in one launch (a device list of 32 x 64 window tiles).  Plane i
+ * for each plane in one launch (a device list of 32 x 32 window tiles).  Plane i
  * writes sse_out[i * r_count + j] and uqi_out[i * r_count + j].  Allocates
  * device memory (tile list and descriptors) -- not a hot call.
  * Errors: as rdct_quality_sweep, plus NO_MEMORY.

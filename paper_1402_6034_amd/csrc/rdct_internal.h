@@ -55,7 +55,7 @@ struct QPlane {
   const uint8_t* src;
   int64_t pitch;
   int32_t width, height;     // multiples of 8
-  int32_t tiles_x, tiles_y;  // tiles of 32 x 64 windows
+  int32_t tiles_x, tiles_y;  // tiles of 32 x 32 windows
   uint64_t* sse;             // r_count accumulators
   int64_t* uqi;              // r_count accumulators (2^-32 units)
 };

@@ -2,17 +2,18 @@
 // of Section 3: the approximation against the exact DCT and the signed DCT,
 // scored by SSE and by the universal quality index, UQI).
 //
-// A workgroup owns a tile of 32 x 64 window positions (8x8 windows at stride 1);
-// the windows reach 7 pixels further, so the tile transforms the 5 x 9 blocks
-// covering 40 x 72 pixels.  It computes every block's coefficients once
-// (Y = F A F^T), then for r = 1, 2, ... adds the basis image of the zig-zag
-// position of rank r - 1, scaled by that coefficient, to the reconstruction it
+// A workgroup owns a tile of 32 x 32 window positions (8x8 windows at stride 1);
+// the windows reach 7 pixels further, so the tile transforms the 5 x 5 blocks
+// covering 40 x 40 pixels.  For r = 1, 2, ... it forms coefficient (k, l) of
+// zig-zag rank r - 1 of every block (Y = F A F^T, eight lanes per block) and
+// adds its basis image, scaled by that coefficient, to the reconstruction it
 // keeps in LDS -- the keep-r reconstruction is linear in the kept
 // coefficients -- and, for the requested r, scores:
-//   SSE  over the 32 x 64 pixels the tile owns (its 4 x 8 blocks);
-//   UQI  over its 32 x 64 windows: each thread owns one window column and eight
-//        window rows, forms 8-pixel row sums of y, y^2 and x y, and slides a
-//        window of eight of them down the column.
+//   SSE  over the 32 x 32 pixels the tile owns (its 4 x 4 blocks);
+//   UQI  over its 32 x 32 windows, from separable box sums: one thread per
+//        (pixel row, 8 window columns) slides an 8-pixel window along the row
+//        and stores the row sums of y, y^2 and x y in LDS; then one thread per
+//        (window column, 4 window rows) slides 8 of those down the column.
 // For the round-off and signed transforms the reconstruction is kept as an
 // integer numerator (A' = numerator / D) and every window or error sum is an
 // exact integer in float64.  No MFMA: per r the work is a rank-1 update and
@@ -24,11 +25,22 @@ namespace rdct {
 
 #define RDCT_CONST __attribute__((address_space(4)))
 
-constexpr int kWinRows = 32, kWinCols = 64;             // windows per tile
-constexpr int kPixRows = kWinRows + 8, kPixCols = kWinCols + 8;  // 40 x 72
-constexpr int kBlkRows = kPixRows / 8, kBlkCols = kPixCols / 8;  // 5 x 9
-constexpr int kTileBlocks = kBlkRows * kBlkCols;        // 45
+constexpr int kWinRows = 32, kWinCols = 32;             // windows per tile
+constexpr int kPixRows = kWinRows + 8, kPixCols = kWinCols + 8;  // 40 x 40
+constexpr int kBlkRows = kPixRows / 8, kBlkCols = kPixCols / 8;  // 5 x 5
+constexpr int kTileBlocks = kBlkRows * kBlkCols;        // 25
 constexpr int kThreads = 256;
+// Row strides (elements): odd numbers of doubles put consecutive rows on
+// different LDS banks.
+constexpr int kYStride = kPixCols + 1;                  // 41
+constexpr int kHStride = kWinCols + 1;                  // 33
+constexpr int kSeg = 8;                                 // window columns per row task
+constexpr int kRowTasks = kPixRows * (kWinCols / kSeg); // 160
+constexpr int kColGroups = kThreads / kWinCols;         // 8
+constexpr int kWinPerThread = kWinRows / kColGroups;    // 4 window rows per thread
+constexpr int kSumRows = kWinPerThread + 7;             // 11 row sums per thread
+static_assert(kTileBlocks * 8 <= kThreads, "eight lanes per block");
+static_assert(kRowTasks <= kThreads, "one row task per thread");
 
 __constant__ ZigZag c_zz_quality = make_zigzag();
 
@@ -49,44 +61,99 @@ __device__ __forceinline__ const RDCT_CONST QualityArgs* quality_args() {
   return (const RDCT_CONST QualityArgs*)(seg + offsetof(KA, A));
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// A float64 moved between lanes by a DPP control (two 32-bit halves); lanes the
+// control does not write, or whose source is out of range, get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, true);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the wave, complete in lane 63: shifts by 1, 2, 4, 8 within each row
+// of 16 lanes leave every row's total in its lane 15; row 15's lane then adds
+// into rows 1 and 3, and lane 31 into rows 2 and 3.  No LDS round trips.
+__device__ __forceinline__ double wave_sum_to_63(double v) {
+  v += dpp_f64<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+  v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
   return v;
 }
 
-// Q of one window from its sums (numerators of y = numerator / D; N = 64).
-// Float64 noise must not decide the index: a constant block keeps only its DC
-// term and is exact in real arithmetic, but the float64 transforms leave ~1e-13
-// of noise in it.  So, in grey levels, a reconstruction window with variance
-// <= 2^-24 counts as flat (no variance, no covariance), a window mean of
-// magnitude <= 2^-24 counts as 0, and a flat pixel window has no covariance.
-// With integer numerators every quantity here is an exact integer and the
-// rules are decided exactly.
-__device__ __forceinline__ double window_uqi(double sx, double sxx, double sy, double syy,
+// Sum over each aligned group of 8 lanes, in all 8: pairs and quads by quad
+// permutations, then the two quads of the group by the half-row mirror.
+__device__ __forceinline__ double block_sum8(double v) {
+  v += dpp_f64<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141, 0xf>(v);   // row_half_mirror
+  return v;
+}
+
+// num / den for den > 0 in the range of window terms: reciprocal estimate, two
+// Newton steps and a residual correction (within an ulp of the rounded quotient).
+__device__ __forceinline__ double quotient(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = __builtin_fma(r, __builtin_fma(-den, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-den, r, 1.0), r);
+  const double q = num * r;
+  return __builtin_fma(__builtin_fma(-den, q, num), r, q);
+}
+
+// Terms of one window's index that depend on the original pixels only
+// (sx = sum x, sxx = sum x^2 over the window; N = 64; D the numerator scale).
+struct WinX {
+  double vx;     // N^2 var_x
+  double dvx;    // D^2 N^2 var_x
+  double dsx2;   // 2 D sx
+  double dsxx;   // D^2 sx^2
+};
+
+__device__ __forceinline__ WinX window_x(double sx, double sxx, double d) {
+  WinX w;
+  w.vx = __builtin_fma(64.0, sxx, -sx * sx);
+  w.dvx = d * d * w.vx;
+  w.dsx2 = 2.0 * d * sx;
+  w.dsxx = d * d * sx * sx;
+  return w;
+}
+
+// Q of one window from its sums (numerators of y = numerator / D; N = 64):
+// Q = [2 cov / (var_x + var_y)] [2 mx my / (mx^2 + my^2)], each factor 1 when
+// its denominator is 0.  Float64 noise must not decide the index: a constant
+// block keeps only its DC term and is exact in real arithmetic, but the float64
+// transforms leave ~1e-13 of noise in it.  So, in grey levels, a
+// reconstruction window with variance <= 2^-24 counts as flat (no variance, no
+// covariance), a window mean of magnitude <= 2^-24 counts as 0, and a flat
+// pixel window has no covariance.  With integer numerators every quantity here
+// is an exact integer and the rules are decided exactly.  The two factors
+// share one division.
+__device__ __forceinline__ double window_uqi(const WinX& w, double sx, double sy, double syy,
                                              double sxy, double d) {
   constexpr double N = 64.0, EPS = 0x1p-24;
-  const double vx = __builtin_fma(N, sxx, -sx * sx);                  // N^2 var_x
   const double vy_raw = __builtin_fma(N, syy, -sy * sy);              // N^2 D^2 var_y
   const bool flat_y = vy_raw <= (N * N) * (d * d) * EPS;
   const double vy = flat_y ? 0.0 : vy_raw;
-  const double cov = (vx == 0.0 || flat_y) ? 0.0 : __builtin_fma(N, sxy, -sx * sy);  // N^2 D cov
+  const double cov = (w.vx == 0.0 || flat_y) ? 0.0 : __builtin_fma(N, sxy, -sx * sy);
   const double sym = __builtin_fabs(sy) <= N * d * EPS ? 0.0 : sy;
-  const double ns = 2.0 * d * cov;
-  const double ds = __builtin_fma(d * d, vx, vy);
-  const double nm = 2.0 * d * sx * sym;
-  const double dm = __builtin_fma(d * d, sx * sx, sym * sym);
-  const double fs = ds == 0.0 ? 1.0 : ns / ds;
-  const double fm = dm == 0.0 ? 1.0 : nm / dm;
-  return fs * fm;
+  const double ds = w.dvx + vy;                                       // D^2 N^2 (var_x + var_y)
+  const double dm = __builtin_fma(sym, sym, w.dsxx);                  // N^2 D^2 (mx^2 + my^2)
+  const bool zs = ds == 0.0, zm = dm == 0.0;
+  const double ns = zs ? 1.0 : 2.0 * d * cov;
+  const double nm = zm ? 1.0 : w.dsx2 * sym;
+  return quotient(ns * nm, (zs ? 1.0 : ds) * (zm ? 1.0 : dm));
 }
 
 __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST QualityArgs* A) {
-  __shared__ double s_coef[kTileBlocks][64];
-  __shared__ double s_y[kPixRows][kPixCols];
-  __shared__ float s_x[kPixRows][kPixCols];
+  __shared__ double s_y[kPixRows][kYStride];
+  __shared__ float s_x[kPixRows][kYStride];
+  __shared__ double s_h[3][kPixRows][kHStride];     // row sums of y, y^2, x y
   __shared__ double s_F[64], s_G[64];
-  __shared__ double s_red[2][kThreads / 64];
+  __shared__ double s_red[2][2][kThreads / 64];    // (UQI, SSE) x (r & 1) x wave
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -111,149 +178,203 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
   else if (t < 128) s_G[t - 64] = A->T.G[t - 64];
   __syncthreads();
 
-  // Forward: Y_b = F A_b F^T, one (block, row k) task per thread.
-  for (int task = t; task < kTileBlocks * 8; task += kThreads) {
-    const int b = task >> 3, k = task & 7;
-    const int br = b / kBlkCols, bc = b - br * kBlkCols;
-    double u[8];
+  // Thread (block ub, index ui): the eight lanes of a block hold its pixel
+  // columns; coefficient (k, l) of Y_b = F A_b F^T is formed when it is needed,
+  // as sum_n (sum_m F[k][m] A[m][n]) F[l][n], lane n taking column n.
+  const int ub = t >> 3, ui = t & 7;
+  const int ubr = ub / kBlkCols, ubc = ub - ubr * kBlkCols;
+  const bool u_on = ub < kTileBlocks && by0 + ubr < nby && bx0 + ubc < nbx;
+  double xcol[8];
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) acc = __builtin_fma(s_F[k * 8 + m], (double)s_x[br * 8 + m][bc * 8 + n], acc);
-      u[n] = acc;
-    }
-#pragma unroll
-    for (int l = 0; l < 8; ++l) {
-      double acc = 0.0;
-#pragma unroll
-      for (int n = 0; n < 8; ++n) acc = __builtin_fma(u[n], s_F[l * 8 + n], acc);
-      s_coef[b][k * 8 + l] = acc;
-    }
-  }
+  for (int m = 0; m < 8; ++m) xcol[m] = u_on ? (double)s_x[ubr * 8 + m][ubc * 8 + ui] : 0.0;
 
-  // Window sums of x (exact integers), for this thread's window column c and
-  // window rows 8 g .. 8 g + 7.
-  const int c = lane, g = wave;
-  double sx[8], sxx[8];
+  // This thread's windows: column c, rows 4 g .. 4 g + 3.  Their sums of x and
+  // x^2 (exact integers) and the terms built from them.
+  const int c = t & (kWinCols - 1), g = t / kWinCols;
+  WinX wx[kWinPerThread];
+  double sxw[kWinPerThread], kq[kWinPerThread];
+  bool w_ok[kWinPerThread], x_special[kWinPerThread];
   {
-    double hx[15], hxx[15];
+    double hx[kSumRows], hxx[kSumRows];
 #pragma unroll
-    for (int rr = 0; rr < 15; ++rr) {
+    for (int rr = 0; rr < kSumRows; ++rr) {
       double a = 0.0, a2 = 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double xv = (double)s_x[8 * g + rr][c + u];
+        const double xv = (double)s_x[kWinPerThread * g + rr][c + u];
         a += xv;
         a2 = __builtin_fma(xv, xv, a2);
       }
       hx[rr] = a;
       hxx[rr] = a2;
     }
+    const bool col_ok = x0 + c + 8 <= P.width;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
+    for (int m = 0; m < kWinPerThread; ++m) {
       double a = 0.0, a2 = 0.0;
 #pragma unroll
       for (int rr = 0; rr < 8; ++rr) {
         a += hx[m + rr];
         a2 += hxx[m + rr];
       }
-      sx[m] = a;
-      sxx[m] = a2;
+      sxw[m] = a;
+      wx[m] = window_x(a, a2, D);
+      w_ok[m] = col_ok && (y0 + kWinPerThread * g + m + 8 <= P.height);
+      x_special[m] = wx[m].vx == 0.0 || a == 0.0;
+      kq[m] = w_ok[m] ? 2.0 * D * wx[m].dsx2 : 0.0;   // 4 D^2 sx, 0 off the plane
     }
   }
-  const bool col_ok = x0 + c + 8 <= P.width;
-  // Owned pixels for the SSE: row t / 8, columns 8 (t % 8) .. + 7 of the tile.
-  const int orow = t >> 3, ocol = (t & 7) * 8;
-  const bool own_ok = (y0 + orow < P.height) && (x0 + ocol < P.width);
+  // Thresholds of the flat and zero-mean rules in numerator units.
+  const double flat_lim = (64.0 * 64.0) * (D * D) * 0x1p-24, mean_lim = 64.0 * D * 0x1p-24;
+  // Row task: pixel row hr, window columns 8 hs .. 8 hs + 7.
+  const int hr = t % kPixRows, hs = t / kPixRows;
+  // Owned pixels for the SSE: row t / 8, columns 4 (t % 8) .. + 3 of the tile.
+  const int orow = t >> 3, ocol = (t & 7) * 4;
+  const bool own_row = y0 + orow < P.height;
   __syncthreads();
 
   const int r_first = A->r_first, r_last = A->r_first + A->r_count - 1;
-  for (int r = 1; r <= r_last; ++r) {
+  // Add coefficient (k, l) of rank r - 1 of every block times its basis image
+  // G[:, k] G[:, l]^T.
+  auto add_basis = [&](int r) {
+    if (!u_on) return;
     const int kl = c_zz_quality.order[r - 1];
     const int k = kl >> 3, l = kl & 7;
-    // Add coefficient (k, l) of every block times its basis image
-    // G[:, k] G[:, l]^T.
-    double gl[8];
+    double u = 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) gl[j] = A->T.G[j * 8 + l];
-    for (int task = t; task < kTileBlocks * 8; task += kThreads) {
-      const int b = task >> 3, i = task & 7;
-      const int br = b / kBlkCols, bc = b - br * kBlkCols;
-      if (by0 + br >= nby || bx0 + bc >= nbx) continue;   // block outside the plane
-      const double ci = s_coef[b][kl] * s_G[i * 8 + k];
-      double* row = &s_y[br * 8 + i][bc * 8];
+    for (int m = 0; m < 8; ++m) u = __builtin_fma(A->T.F[k * 8 + m], xcol[m], u);
+    const double coef = block_sum8(u * s_F[l * 8 + ui]);
+    const double ci = coef * s_G[ui * 8 + k];
+    double* row = &s_y[ubr * 8 + ui][ubc * 8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) row[j] = __builtin_fma(ci, gl[j], row[j]);
+    for (int j = 0; j < 8; ++j) row[j] = __builtin_fma(ci, A->T.G[j * 8 + l], row[j]);
+  };
+  // The tile's sums for r (the waves' totals, in LDS slot r & 1) to the outputs.
+  auto flush = [&](int r) {
+    double q = 0.0, e = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      q += s_red[0][r & 1][w];
+      e += s_red[1][r & 1][w];
     }
-    __syncthreads();
-    if (r >= r_first) {
-      // UQI of the eight windows of this thread.
-      double q_acc = 0.0;
-      {
-        double hy[15], hyy[15], hxy[15];
-        double sy = 0.0, syy = 0.0, sxy = 0.0;
+    const int o = r - r_first;
+    atomicAdd(reinterpret_cast<unsigned long long*>(P.uqi + o),
+              (unsigned long long)(long long)__builtin_rint(q * 4294967296.0));
+    // Exact families: e is an integer below 2^53; otherwise 2^-20 units.
+    const double eu = exact ? e : __builtin_rint(e * 1048576.0);
+    atomicAdd(reinterpret_cast<unsigned long long*>(P.sse + o), (unsigned long long)eu);
+  };
+
+  // Two barriers per r: row sums and SSE of r | window sums of r, and the basis
+  // update for r + 1 (which only the next row sums read).
+  add_basis(1);
+  __syncthreads();
+  for (int r = 1; r <= r_last; ++r) {
+    const bool scored = r >= r_first;
+    if (scored) {
+      // Row sums over 8 pixels, sliding along the row.
+      if (t < kRowTasks) {
+        const double* yr = &s_y[hr][kSeg * hs];
+        const float* xr = &s_x[hr][kSeg * hs];
+        double yv[kSeg + 7], xv[kSeg + 7];
 #pragma unroll
-        for (int rr = 0; rr < 15; ++rr) {
-          double a = 0.0, a2 = 0.0, ax = 0.0;
+        for (int u = 0; u < kSeg + 7; ++u) {
+          yv[u] = yr[u];
+          xv[u] = (double)xr[u];
+        }
+        double a = 0.0, a2 = 0.0, ax = 0.0;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double yv = s_y[8 * g + rr][c + u];
-            const double xv = (double)s_x[8 * g + rr][c + u];
-            a += yv;
-            a2 = __builtin_fma(yv, yv, a2);
-            ax = __builtin_fma(xv, yv, ax);
+        for (int u = 0; u < 8; ++u) {
+          a += yv[u];
+          a2 = __builtin_fma(yv[u], yv[u], a2);
+          ax = __builtin_fma(xv[u], yv[u], ax);
+        }
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+          if (j > 0) {
+            a += yv[j + 7] - yv[j - 1];
+            a2 = __builtin_fma(-yv[j - 1], yv[j - 1], __builtin_fma(yv[j + 7], yv[j + 7], a2));
+            ax = __builtin_fma(-xv[j - 1], yv[j - 1], __builtin_fma(xv[j + 7], yv[j + 7], ax));
           }
-          hy[rr] = a;
-          hyy[rr] = a2;
-          hxy[rr] = ax;
-          sy += a;
-          syy += a2;
-          sxy += ax;
-          if (rr >= 7) {
-            const int m = rr - 7;
-            const bool ok = col_ok && (y0 + 8 * g + m + 8 <= P.height);
-            const double q = window_uqi(sx[m], sxx[m], sy, syy, sxy, D);
-            q_acc += ok ? q : 0.0;
-            sy -= hy[m];
-            syy -= hyy[m];
-            sxy -= hxy[m];
-          }
+          s_h[0][hr][kSeg * hs + j] = a;
+          s_h[1][hr][kSeg * hs + j] = a2;
+          s_h[2][hr][kSeg * hs + j] = ax;
         }
       }
       // Squared error over the owned pixels: (D x - numerator)^2.
       double e_acc = 0.0;
-      if (own_ok) {
+      if (own_row) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 4; ++j) {
+          const bool in = x0 + ocol + j < P.width;
           const double e = __builtin_fma(D, (double)s_x[orow][ocol + j], -s_y[orow][ocol + j]);
-          e_acc = __builtin_fma(e, e, e_acc);
+          e_acc = in ? __builtin_fma(e, e, e_acc) : e_acc;
         }
       }
-      q_acc = wave_sum_f64(q_acc);
-      e_acc = wave_sum_f64(e_acc);
-      if (lane == 0) {
-        s_red[0][wave] = q_acc;
-        s_red[1][wave] = e_acc;
-      }
-      __syncthreads();
-      if (t == 0) {
-        double q = 0.0, e = 0.0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-          q += s_red[0][w];
-          e += s_red[1][w];
-        }
-        const int o = r - r_first;
-        atomicAdd(reinterpret_cast<unsigned long long*>(P.uqi + o),
-                  (unsigned long long)(long long)__builtin_rint(q * 4294967296.0));
-        // Exact families: e is an integer below 2^53; otherwise 2^-20 units.
-        const double eu = exact ? e : __builtin_rint(e * 1048576.0);
-        atomicAdd(reinterpret_cast<unsigned long long*>(P.sse + o), (unsigned long long)eu);
-      }
+      e_acc = wave_sum_to_63(e_acc);
+      if (lane == 63) s_red[1][r & 1][wave] = e_acc;
     }
+    if (t == 0 && r - 1 >= r_first) flush(r - 1);
+    __syncthreads();
+
+    if (scored) {
+      // Window sums down the column, and the index of each window.
+      double hy[kSumRows], hyy[kSumRows], hxy[kSumRows];
+#pragma unroll
+      for (int rr = 0; rr < kSumRows; ++rr) {
+        hy[rr] = s_h[0][kWinPerThread * g + rr][c];
+        hyy[rr] = s_h[1][kWinPerThread * g + rr][c];
+        hxy[rr] = s_h[2][kWinPerThread * g + rr][c];
+      }
+      double sy = 0.0, syy = 0.0, sxy = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        sy += hy[rr];
+        syy += hyy[rr];
+        sxy += hxy[rr];
+      }
+      double wy[kWinPerThread], wyy[kWinPerThread], wxy[kWinPerThread];
+      bool special = false;
+#pragma unroll
+      for (int m = 0; m < kWinPerThread; ++m) {
+        if (m > 0) {
+          sy += hy[m + 7] - hy[m - 1];
+          syy += hyy[m + 7] - hyy[m - 1];
+          sxy += hxy[m + 7] - hxy[m - 1];
+        }
+        wy[m] = sy;
+        wyy[m] = syy;
+        wxy[m] = sxy;
+        // Windows that need one of the rules of window_uqi: a flat or zero-mean
+        // reconstruction, or a flat or zero pixel window.
+        special |= (__builtin_fma(64.0, syy, -sy * sy) <= flat_lim) |
+                   (__builtin_fabs(sy) <= mean_lim) | x_special[m];
+      }
+      double q_acc = 0.0;
+      if (__ballot(special) == 0) {
+        // No rule applies anywhere in the wave: both factors have nonzero
+        // denominators, Q = 4 D^2 sx cov sy / ((D^2 vx + vy)(sy^2 + D^2 sx^2)).
+#pragma unroll
+        for (int m = 0; m < kWinPerThread; ++m) {
+          const double vy = __builtin_fma(64.0, wyy[m], -wy[m] * wy[m]);
+          const double cov = __builtin_fma(64.0, wxy[m], -sxw[m] * wy[m]);
+          const double den = (wx[m].dvx + vy) * __builtin_fma(wy[m], wy[m], wx[m].dsxx);
+          q_acc += quotient(kq[m] * cov * wy[m], den);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < kWinPerThread; ++m) {
+          const double q = window_uqi(wx[m], sxw[m], wy[m], wyy[m], wxy[m], D);
+          q_acc += w_ok[m] ? q : 0.0;
+        }
+      }
+      q_acc = wave_sum_to_63(q_acc);
+      if (lane == 63) s_red[0][r & 1][wave] = q_acc;
+    }
+    if (r < r_last) add_basis(r + 1);
     __syncthreads();
   }
+  if (t == 0) flush(r_last);
 }
 
 __global__ __launch_bounds__(kThreads) void k_quality(QPlane P, QualityArgs /*A*/) {

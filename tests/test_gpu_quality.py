@@ -4,7 +4,7 @@ variant, for every r of a sweep.
 
 Bars: SSE bit-exact for the transforms with integer numerators (round-off:
 units 1/576^2, signed DCT: 1/64^2); float transforms within one 2^-21 per
-32 x 64 tile plus 1e-9 relative.  Mean UQI within the output's
+32 x 32 tile plus 1e-9 relative.  Mean UQI within the output's
 fixed-point step (2^-33 per tile, averaged over the windows) plus 1e-12 of the
 exact-integer oracle (round-off, signed DCT), or plus 1e-9 of the float64
 oracle (DCT, ceiling) on planes with no flat window, where float64 sums are
@@ -34,7 +34,7 @@ def host(t):
 
 
 def n_tiles(h, w):
-    return -(-h // 32) * -(-w // 64)
+    return -(-h // 32) * -(-w // 32)
 
 
 def check(img, t, r_first, r_count, sse_raw, uqi_raw):
