@@ -588,6 +588,47 @@ WORKLOADS = {"frame": FrameQuant, "sweep": RetentionSweep, "ragged": RaggedBatch
              "quality": QualitySweep, "codec": CodecFrame}
 
 
+def _pool_worker(job):
+    """One worker of the multi-core oracle baseline: renders its planes on the
+    CPU (not timed) and times the oracle on each until its budget is spent."""
+    budget_s, items = job
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    from paper_1402_6034_amd import synth
+    blocks, spent = 0, 0.0
+    with threadpool_limits(limits=1):
+        for it in items:
+            img = synth.render_np(it.seed, it.height, it.width)
+            t0 = time.perf_counter()
+            O.quant_eval(img, O.quant_table(it.quality))
+            spent += time.perf_counter() - t0
+            blocks += (it.height // 8) * (it.width // 8)
+            if spent > budget_s:
+                break
+    return blocks, spent
+
+
+def cpu_pool_baseline(budget_s):
+    """The oracle on the ragged batch's planes over a pool of processes, one per
+    core available to this process (at most 16), each single-threaded.  Runs
+    before the GPU is initialised (the workers are forked).  Value: the sum of
+    the workers' own rates (rendering excluded)."""
+    import multiprocessing as mp
+    from paper_1402_6034_amd import synth
+    cores = min(16, len(os.sched_getaffinity(0)))
+    items = sorted(synth.ragged_batch(0, 1000), key=lambda it: it.height * it.width)
+    jobs = [(budget_s, items[k::cores]) for k in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_pool_worker, jobs)
+    rate = sum(b / t for b, t in res if t > 0) / 1e6
+    blocks = sum(b for b, _ in res)
+    return {"value": rate, "unit": "Mblocks/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} single-threaded processes, each on every {cores}-th of the 1000 "
+                      f"planes in size order for ~{budget_s:g} s of oracle time ({blocks} blocks "
+                      "in all; planes rendered on the CPU, same generator and sizes); forward + "
+                      "exact quantisation + float64 inverse + SSE"}
+
+
 def _oracle_threads():
     """The oracle runs in one process with its BLAS pool limited to one thread
     (see main), so it uses one core."""
@@ -610,6 +651,9 @@ def main():
                     help="ragged, sweep, quality: .npy file holding the rendered planes (written if absent)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-pool-budget", type=float, default=4.0,
+                    help="ragged: seconds of oracle time per process for the multi-core "
+                         "baseline (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB mebibytes device-to-device 3 times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -620,6 +664,12 @@ def main():
         print("bench.py: this build measures one MI355X only; multi-GPU runs are not provided "
               "(the path would shard by plane; see the design notes).", file=sys.stderr)
         sys.exit(2)
+
+    cpu_pool = None
+    if args.workload == "ragged" and args.cpu_budget > 0 and args.cpu_pool_budget > 0:
+        log("[bench] timing the CPU oracle over a process pool (before GPU start-up)")
+        cpu_pool = cpu_pool_baseline(args.cpu_pool_budget)
+        log(f"[bench] pool oracle: {cpu_pool['value']:.3f} Mblocks/s on {cpu_pool['cores']} cores")
 
     import torch
     from paper_1402_6034_amd import rdct as R
@@ -696,6 +746,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": wl.dtype, "data": "synthetic", "config": wl.config(),
            "roofline": roofline, "cpu_baseline": cpu}
+    if cpu_pool is not None:
+        out["cpu_baseline_pool"] = cpu_pool
     if plain is not None:
         out["plain"] = plain
     if hasattr(wl, "report") and wl.report():
