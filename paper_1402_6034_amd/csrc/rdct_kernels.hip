@@ -473,9 +473,28 @@ __device__ __forceinline__ void chunk_load(const Plane& P, int t0, int lane, Pix
   load_block(P, t0 + 64 + lane, px.vh, px.ah, px.xh, px.yh);
 }
 
+// Error sums of one wave: a lane's part, added to others and written by
+// flush_sums.  EV_SPATIAL / EV_COEF: every lane holds a partial of the plane's
+// one sum.  EV_SWEEP: lane rho holds the dropped energy at rank rho, the sum for
+// r = rho (lanes outside r .. r + r_count - 1 hold nothing that is written).
+template <int EV>
+__device__ __forceinline__ void flush_sums(const Plane& P, uint64_t part, int lane) {
+  if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
+    const uint64_t s = wave_sum_u64(part);
+    if (lane == 0 && s != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(P.sse), (unsigned long long)s);
+  } else if constexpr (EV == EV_SWEEP) {
+    if (lane >= P.r && lane < P.r + P.r_count && part != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(P.sse + (lane - P.r)),
+                (unsigned long long)part);
+  }
+}
+
+// One chunk: outputs written, the lane's part of the error sums returned.
 template <int SEL, int CO, bool RECON, int EV>
-__device__ __forceinline__ void plane_chunk(const Plane& P, QCPtr qc, const Pixels& px, int lane,
-                                            uint32_t* lds_wave, uint8_t* stage_wave) {
+__device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const Pixels& px,
+                                                int lane, uint32_t* lds_wave,
+                                                uint8_t* stage_wave) {
   const int t0 = px.t0;
   const int tl = t0 + lane, th = t0 + 64 + lane;
   const bool vl = px.vl, vh = px.vh;
@@ -540,12 +559,7 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, QCPtr qc, const Pixe
         if constexpr (SP) s += (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
       }
     }
-    if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
-      s = wave_sum_u64(s);
-      if (lane == 0 && s != 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.sse),
-                                         (unsigned long long)s);
-    }
-    return;
+    return s;
   } else {
   const uint64_t keep = P.keep;
   if constexpr (CO != CO_NONE) {
@@ -579,11 +593,7 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, QCPtr qc, const Pixe
       for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
       s += retention_inverse<RECON, SP>(P, v, keep, a, h ? xh : xl, h ? yh : yl, h);
     }
-    if constexpr (SP) {
-      s = wave_sum_u64(s);
-      if (lane == 0 && s != 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.sse),
-                                         (unsigned long long)s);
-    }
+    if constexpr (SP) return s;
   }
 
   if constexpr (EV == EV_SWEEP) {
@@ -609,10 +619,9 @@ __device__ __forceinline__ void plane_chunk(const Plane& P, QCPtr qc, const Pixe
       const uint64_t o = __shfl_down(x, off, 64);
       if (lane + off < 64) x += o;
     }
-    if (lane >= P.r && lane < P.r + P.r_count && x != 0)
-      atomicAdd(reinterpret_cast<unsigned long long*>(P.sse + (lane - P.r)),
-                (unsigned long long)(576ull * x));
+    return 576ull * x;
   }
+  return 0;
   }
 }
 
@@ -636,18 +645,27 @@ struct Prefetch {
 
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void plane_kernel_body(const Plane& P, QCPtr qc) {
-  // One chunk of 128 blocks per wave; the grid covers the plane.
+  // Chunks of 128 blocks: wave w takes chunks w, w + W, ... (W waves in the
+  // grid).  Without error sums the grid covers the plane, one chunk per wave;
+  // with them the grid is capped, so a large plane's sums take one atomic per
+  // wave instead of one per chunk, all on the same address.
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * wpg + wave;
+  const int n_waves = gridDim.x * wpg;
+  int c = blockIdx.x * wpg + wave;
   if (c * 128 >= P.nblocks) return;
   uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
                    wave * wave_stage_bytes<SEL, CO, RECON, EV>();
-  Pixels cur;
-  chunk_load(P, c * 128, lane, cur);
-  plane_chunk<SEL, CO, RECON, EV>(P, qc, cur, lane, lds + wave * (64 * 65), stage);
+  uint64_t acc = 0;
+  for (; c * 128 < P.nblocks; c += n_waves) {
+    Pixels cur;
+    chunk_load(P, c * 128, lane, cur);
+    acc += plane_chunk<SEL, CO, RECON, EV>(P, qc, cur, lane, lds + wave * (64 * 65), stage);
+    if constexpr (EV == EV_NONE) break;
+  }
+  flush_sums<EV>(P, acc, lane);
 }
 
 // The single-plane kernels take the quantisation table by value, so a call needs
@@ -691,6 +709,21 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
   uint32_t* sweep = lds + wave * (64 * 65);
   int it = blockIdx.x * wpg + wave;
   if (it >= n_items) return;
+  // The wave's error parts accumulate while its items stay in one plane and are
+  // written when the plane changes: a large plane gets one atomic per wave
+  // rather than one per item, all on the same address.
+  uint64_t acc = 0;
+  int acc_plane = items[it].plane;
+  auto account = [&](int plane, uint64_t part) {
+    if constexpr (EV != EV_NONE) {
+      if (plane != acc_plane) {
+        flush_sums<EV>(planes[acc_plane], acc, lane);
+        acc = 0;
+        acc_plane = plane;
+      }
+      acc += part;
+    }
+  };
   if constexpr (Prefetch<SEL, RECON, EV>::value) {
     WorkItem w = items[it];
     Pixels cur;
@@ -705,8 +738,8 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
         chunk_load(planes[wn.plane], wn.t0, lane, nxt);
       }
       const Plane& P = planes[w.plane];
-      plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane, sweep,
-                                      stage);
+      account(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
+                                                       sweep, stage));
       if (!more) break;
       cur = nxt;
       w = wn;
@@ -718,10 +751,11 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
       const Plane& P = planes[w.plane];
       Pixels cur;
       chunk_load(P, w.t0, lane, cur);
-      plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane, sweep,
-                                      stage);
+      account(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
+                                                       sweep, stage));
     }
   }
+  if constexpr (EV != EV_NONE) flush_sums<EV>(planes[acc_plane], acc, lane);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
@@ -842,10 +876,18 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
+// Waves per CU that the single-plane kernels keep resident (two per SIMD).
+constexpr int kPlaneWavesPerCU = 8;
+
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg, hipStream_t s) {
+  static const int n_cu = device_cu_count();
   const int chunks = (P.nblocks + 127) / 128;
-  const int grid = (chunks + wpg - 1) / wpg;
+  int grid = (chunks + wpg - 1) / wpg;
+  if constexpr (EV != EV_NONE) {
+    const int cap = n_cu * kPlaneWavesPerCU / wpg;
+    if (grid > cap) grid = cap;
+  }
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
                      (size_t)wpg * wave_stage_bytes<SEL, CO, RECON, EV>();
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
