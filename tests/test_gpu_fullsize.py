@@ -146,3 +146,26 @@ def test_sweep_batched_full():
         ref = O.retention_eval(host(imgs[s]), range(1, 46))
         assert [int(v) for v in sse[s]] == [ref["sse_num"][r] for r in range(1, 46)], s
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["sweep", "quant"])
+def test_frame_error_sums_split_into_bands(frame, mode):
+    """Error sums of the whole 8192 x 8192 frame (capped grid, several chunks per
+    wave, one atomic per wave) equal the sums over four 2048-row bands, each
+    taken alone, and the one-plane batch."""
+    img, _ = frame
+    if mode == "sweep":
+        sel, count = R.select(R.SEL_ZIGZAG, r=1), 45
+    else:
+        sel, count = R.select(R.SEL_QUANT, quality=50, level_shift=128), 1
+    whole, _, _ = R.compress_eval(img, sel, count)
+    whole = host(whole).astype(np.int64)
+    bands = sum(host(R.compress_eval(img[k * 2048:(k + 1) * 2048], sel, count)[0]).astype(np.int64)
+                for k in range(4))
+    assert np.array_equal(whole, bands)
+    plan = R.BatchPlan([img], [sel], None, recon=False, r_count=count)
+    plan.run()
+    assert np.array_equal(host(plan.sse).reshape(-1).astype(np.int64), whole)
+    plan.close()
+    if mode == "sweep":
+        assert np.all(np.diff(whole) <= 0)          # dropping fewer coefficients never adds error
