@@ -52,15 +52,15 @@ namespace {
 
 void free_plan(rdct_batch_plan* p) {
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) {
-    hipStreamSynchronize(p->cap_stream);
-    hipStreamDestroy(p->cap_stream);
+    (void)hipStreamSynchronize(p->cap_stream);
+    (void)hipStreamDestroy(p->cap_stream);
   }
-  if (p->d_planes) hipFree(p->d_planes);
-  if (p->d_tables) hipFree(p->d_tables);
-  if (p->d_items) hipFree(p->d_items);
+  if (p->d_planes) (void)hipFree(p->d_planes);
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_items) (void)hipFree(p->d_items);
   delete p;
 }
 
@@ -79,11 +79,11 @@ hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t
 
 rdct_status_t capture(rdct_batch_plan* p) {
   if (p->exec) {
-    hipGraphExecDestroy(p->exec);
+    (void)hipGraphExecDestroy(p->exec);
     p->exec = nullptr;
   }
   if (p->graph) {
-    hipGraphDestroy(p->graph);
+    (void)hipGraphDestroy(p->graph);
     p->graph = nullptr;
   }
   p->graph_ready = false;
@@ -201,7 +201,10 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   p->n_blocks = n_blocks;
   p->sse = sse_out;
   p->n_cu = device_cu_count();
-  hipGetDevice(&p->device);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return RDCT_ERR_HIP;
+  }
   p->key = plan_key(p);
 
   bool ok = hipMalloc(&p->d_planes, sizeof(Plane) * n) == hipSuccess &&
@@ -312,7 +315,10 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
           break;
         }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = RDCT_ERR_HIP;
+          break;
+        }
         us.push_back(ms * 1000.f);
       }
       if (st != RDCT_OK) break;
@@ -325,8 +331,8 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
     }
     if (st != RDCT_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != RDCT_OK) return st;
   plan->tuning = best_t;
   plan->graph_ready = false;  // re-captured on the next run

@@ -496,7 +496,6 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
                                                 int lane, uint32_t* lds_wave,
                                                 uint8_t* stage_wave) {
   const int t0 = px.t0;
-  const int tl = t0 + lane, th = t0 + 64 + lane;
   const bool vl = px.vl, vh = px.vh;
   const int xl = px.xl, yl = px.yl, xh = px.xh, yh = px.yh;
   const uint32_t (&al)[16] = px.al;

@@ -289,8 +289,23 @@ void run_plain(rdct_server* s, Request& r) {
 }
 
 void worker_main(rdct_server* s) {
-  hipSetDevice(s->device);
+  const bool device_ok = hipSetDevice(s->device) == hipSuccess;
   std::unique_lock<std::mutex> lk(s->mu);
+  if (!device_ok) {
+    // This thread cannot reach the device: every request completes with an error.
+    for (;;) {
+      while (!s->pending.empty()) {
+        Request r = s->pending.front();
+        s->pending.pop_front();
+        release_request(s, r);
+        complete(s, r, RDCT_ERR_HIP, nullptr, s->now_us(), 0);
+        s->st.completed++;
+      }
+      s->cv_done.notify_all();
+      if (s->stop) return;
+      s->cv_work.wait(lk, [&] { return s->stop.load() || !s->pending.empty(); });
+    }
+  }
   for (;;) {
     // Retire finished batches.
     for (auto bi = s->inflight.begin(); bi != s->inflight.end();) {
@@ -315,7 +330,7 @@ void worker_main(rdct_server* s) {
       }
       s->dev.release(bi->dev_off, bi->dev_bytes);
       s->host.release(bi->host_off, bi->host_bytes);
-      hipEventDestroy(bi->done);
+      (void)hipEventDestroy(bi->done);
       s->stream_busy[bi->stream] = false;
       bi = s->inflight.erase(bi);
       s->cv_done.notify_all();
@@ -449,11 +464,11 @@ void destroy(rdct_server* s) {
   }
   for (int i = 0; i < 4; ++i)
     if (s->streams[i]) {
-      hipStreamSynchronize(s->streams[i]);
-      hipStreamDestroy(s->streams[i]);
+      (void)hipStreamSynchronize(s->streams[i]);
+      (void)hipStreamDestroy(s->streams[i]);
     }
-  if (s->dev_base) hipFree(s->dev_base);
-  if (s->host_base) hipHostFree(s->host_base);
+  if (s->dev_base) (void)hipFree(s->dev_base);
+  if (s->host_base) (void)hipHostFree(s->host_base);
   delete s;
 }
 
@@ -474,7 +489,10 @@ rdct_status_t rdct_server_create(const rdct_server_cfg_t* cfg, rdct_server_t** o
   if (!s->cfg.max_batch_planes) s->cfg.max_batch_planes = 4096;
   if (!s->cfg.staging_bytes) s->cfg.staging_bytes = std::min<int64_t>(cfg->budget_bytes / 4, 2ll << 30);
   s->t0 = std::chrono::steady_clock::now();
-  hipGetDevice(&s->device);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return RDCT_ERR_HIP;
+  }
   s->n_cu = device_cu_count();
   // The first 256 bytes of the device budget hold the plain path's error sum.
   if (hipMalloc(&s->dev_base, (size_t)s->cfg.budget_bytes) != hipSuccess ||
