@@ -8,9 +8,9 @@
 // (run, value) pairs -- a count pass, a wave prefix sum, an emit pass into the
 // wave's LDS area at the lane's offset -- and the wave copies the group's
 // pairs contiguously into the group's slot.  The lane then inverts its block
-// and writes clamp(round(A'), 0, 255).  Pack: one workgroup scans the group
-// totals; every group then writes its block offsets and copies its pairs into
-// the packed stream.
+// and writes clamp(round(A'), 0, 255).  Pack: the group totals are scanned in
+// chunks of 256 groups; every group then adds the chunk totals before it, writes
+// its block offsets and copies its pairs into the packed stream.
 #include "rdct_device.h"
 
 namespace rdct {
@@ -170,55 +170,66 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
   }
 }
 
-// Exclusive scan of the group totals (one workgroup of 1024 threads), total in
-// offsets[nblocks].
-__global__ __launch_bounds__(1024) void k_codec_scan(const uint32_t* __restrict__ group_pairs,
-                                                      int32_t n_groups, uint32_t* __restrict__ base,
-                                                      uint32_t* __restrict__ offsets,
-                                                      int32_t nblocks) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int per = (n_groups + 1023) / 1024;
-  const int g0 = t * per;
-  uint32_t s = 0;
-  for (int i = 0; i < per; ++i)
-    if (g0 + i < n_groups) s += group_pairs[g0 + i];
-  part[t] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const uint32_t u = t >= d ? part[t - d] : 0u;
-    __syncthreads();
-    part[t] += u;
-    __syncthreads();
+// Offsets of the groups' pairs, in two steps with no single-workgroup stage
+// (one workgroup scanning every total is bound by its own memory latency).
+// k_codec_scan: workgroup c takes the chunk of kScanChunk consecutive groups
+// and writes each group's exclusive prefix within its chunk to local[].
+// k_codec_pack: the wave of group g adds the totals of the chunks before its
+// own (chunk total = last group's local prefix + its pair count) to local[g].
+constexpr int kScanChunk = 256;
+
+__global__ __launch_bounds__(kScanChunk) void k_codec_scan(
+    const uint32_t* __restrict__ group_pairs, int32_t n_groups, uint32_t* __restrict__ local) {
+  __shared__ uint32_t wave_tot[kScanChunk / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = blockIdx.x * kScanChunk + t;
+  const uint32_t v = g < n_groups ? group_pairs[g] : 0u;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
   }
-  uint32_t run = part[t] - s;   // exclusive prefix of this thread's range
-  for (int i = 0; i < per; ++i)
-    if (g0 + i < n_groups) {
-      base[g0 + i] = run;
-      run += group_pairs[g0 + i];
-    }
-  if (t == 1023) offsets[nblocks] = part[1023];
+  if (lane == 63) wave_tot[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int w = 0; w < kScanChunk / 64; ++w) before += w < wave ? wave_tot[w] : 0u;
+  if (g < n_groups) local[g] = before + inc - v;
 }
 
-// One wave per group: block offsets and the copy of the group's pairs.
+// One wave per group: the group's offset, its blocks' offsets and the copy of
+// its pairs.
 __global__ __launch_bounds__(64) void k_codec_pack(const uint16_t* __restrict__ counts,
                                                    const uint32_t* __restrict__ group_pairs,
                                                    const int32_t* __restrict__ slots,
-                                                   const uint32_t* __restrict__ base,
-                                                   int32_t nblocks, uint32_t* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ local,
+                                                   int32_t n_groups, int32_t nblocks,
+                                                   uint32_t* __restrict__ offsets,
                                                    int32_t* __restrict__ packed, int64_t capacity) {
   const int g = blockIdx.x, lane = threadIdx.x;
+  // Totals of the chunks before this group's (all of them full chunks).
+  const int chunk = g / kScanChunk;
+  uint32_t prev = 0;
+  for (int c = lane; c < chunk; c += 64) {
+    const int last = c * kScanChunk + kScanChunk - 1;
+    prev += local[last] + group_pairs[last];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) prev += __shfl_xor(prev, d, 64);
+  const uint32_t b = prev + local[g];
+  const uint32_t n = group_pairs[g];
+  if (g == n_groups - 1 && lane == 0) offsets[nblocks] = b + n;
+
   const int t = g * kGroup + lane;
-  const int c = t < nblocks ? (int)counts[t] : 0;
-  int off = c;
+  const int cnt = t < nblocks ? (int)counts[t] : 0;
+  int off = cnt;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const int u = __shfl_up(off, d, 64);
     if (lane >= d) off += u;
   }
-  const uint32_t b = base[g];
-  if (t < nblocks) offsets[t] = b + (uint32_t)(off - c);
-  const uint32_t n = group_pairs[g];
+  if (t < nblocks) offsets[t] = b + (uint32_t)(off - cnt);
   const int32_t* src = slots + (int64_t)g * kSlot;
   for (uint32_t i = lane; i < n; i += 64)
     if ((int64_t)b + i < capacity) packed[b + i] = src[i];
@@ -244,10 +255,10 @@ hipError_t launch_codec_pack(const uint16_t* counts, const uint32_t* group_pairs
                              hipStream_t s) {
   const int groups = (nblocks + kGroup - 1) / kGroup;
   if (groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codec_scan, dim3(1), dim3(1024), 0, s, group_pairs, groups, workspace,
-                     offsets, nblocks);
+  hipLaunchKernelGGL(k_codec_scan, dim3((groups + kScanChunk - 1) / kScanChunk),
+                     dim3(kScanChunk), 0, s, group_pairs, groups, workspace);
   hipLaunchKernelGGL(k_codec_pack, dim3(groups), dim3(64), 0, s, counts, group_pairs, slots,
-                     workspace, nblocks, offsets, packed, capacity);
+                     workspace, groups, nblocks, offsets, packed, capacity);
   return hipGetLastError();
 }
 
