@@ -162,6 +162,19 @@ class FrameQuant:
                           "forward + exact quantisation"}
 
 
+def read_back(dev, owner):
+    """The device tensor's values on the host, through a pinned buffer kept on
+    `owner` (an asynchronous copy on the current stream, then its completion)."""
+    import torch
+    buf = getattr(owner, "_pinned", None)
+    if buf is None or buf.shape != dev.shape or buf.dtype != dev.dtype:
+        buf = torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True)
+        owner._pinned = buf
+    buf.copy_(dev, non_blocking=True)
+    torch.cuda.current_stream().synchronize()
+    return buf.numpy()
+
+
 def seeded_planes(n, size, planes_cache=None):
     """Planes 0..n-1 of size x size from the synthetic generator, on the device.
     With planes_cache, loaded from (or first written to) that .npy file, so a
@@ -210,7 +223,7 @@ class RetentionSweep:
     def step(self):
         import numpy as np
         self.plan.run()
-        s = self.plan.sse.cpu().numpy().astype(np.float64) / 576.0 ** 2
+        s = read_back(self.plan.sse, self).astype(np.float64) / 576.0 ** 2
         mse = s / float(self.size * self.size)
         with np.errstate(divide="ignore"):
             self.psnr = 10.0 * np.log10(255.0 ** 2 / mse)
@@ -473,10 +486,11 @@ class RaggedBatch:
     def step(self):
         import numpy as np
         self.plan.run()
-        s = self.plan.sse.cpu().numpy().astype(np.float64) * 2.0 ** -20
-        npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
+        s = read_back(self.plan.sse, self).astype(np.float64) * 2.0 ** -20
+        if getattr(self, "npx", None) is None:
+            self.npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
         with np.errstate(divide="ignore"):
-            self.psnr = 10.0 * np.log10(255.0 ** 2 / (s / npx))
+            self.psnr = 10.0 * np.log10(255.0 ** 2 / (s / self.npx))
 
     blocks_per_step = property(lambda self: self.nb)
     bytes_per_block = 64 + 128 + 256
