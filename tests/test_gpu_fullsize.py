@@ -8,6 +8,7 @@ size-independent properties (batch == single plane, sums over blocks).
   * sweep   256 planes of 512 x 512, keep r = 1..45 (one batch launch, and
             one launch per plane)
   * codec   the 8192 x 8192 frame through encode + pack
+  * comparison  one plan per transform over the sweep's 256 planes, r = 1..45
 """
 import numpy as np
 import pytest
@@ -169,3 +170,36 @@ def test_frame_error_sums_split_into_bands(frame, mode):
     plan.close()
     if mode == "sweep":
         assert np.all(np.diff(whole) <= 0)          # dropping fewer coefficients never adds error
+
+
+def test_quality_plan_full_sampled():
+    """The comparison workload as timed: one plan per transform over the 256
+    planes of 512 x 512, r = 1..45.  Two sampled planes against the oracle at
+    r = 1, 10, 45 (exact for the integer transforms), and the plan's rows equal
+    the same planes swept alone."""
+    imgs = [synth.render(s, 512, 512, device=DEV) for s in range(256)]
+    nwin = 505 * 505
+    quant = (16 * 16) * 2.0 ** -33 / nwin
+    for t, name in ((R.T_DCT, "dct"), (R.T_RDCT, "rdct"), (R.T_SDCT, "sdct")):
+        plan = R.QualityPlan(imgs, t, 1, 45)
+        plan.run()
+        sse, uqi = host(plan.sse).astype(np.int64), host(plan.uqi).astype(np.int64)
+        for s in (5, 200):
+            s1, u1 = R.quality_sweep(imgs[s], t, 1, 45)
+            assert np.array_equal(host(s1).astype(np.int64), sse[s]), (name, s)
+            assert np.array_equal(host(u1).astype(np.int64), uqi[s]), (name, s)
+            x = host(imgs[s]).astype(np.int64)
+            for r in (1, 10, 45):
+                got_u = int(uqi[s, r - 1]) * 2.0 ** -32 / nwin
+                if t == R.T_DCT:
+                    rec = O.retention_recon(x.astype(np.uint8), name, r)
+                    want = float(np.sum((x - rec) ** 2))
+                    got = int(sse[s, r - 1]) * 2.0 ** -20
+                    assert abs(got - want) <= 256 * 2.0 ** -21 + 1e-9 * want, (name, s, r)
+                    assert abs(got_u - O.uqi(x, rec)) <= quant + 1e-9, (name, s, r)
+                else:
+                    num, d = O.integer_numerators(x.astype(np.uint8), name, r)
+                    assert int(sse[s, r - 1]) == int(np.sum((d * x - num) ** 2)), (name, s, r)
+                    want_u = float(np.mean(O.uqi_map_exact(x, num, d)))
+                    assert abs(got_u - want_u) <= quant + 1e-12, (name, s, r)
+        plan.close()
