@@ -675,8 +675,9 @@ def main():
     if args.serve_requests is None:
         args.serve_requests = 4000 if args.workload == "ragged" else 0
     if args.gpus != 1:
-        print("bench.py: this build measures one MI355X only; multi-GPU runs are not provided "
-              "(the path would shard by plane; see the design notes).", file=sys.stderr)
+        print("bench.py: measures one MI355X only; runs on several GPUs are not provided "
+              "(planes and requests would shard across GPUs with no exchange but the per-plane "
+              "error sums).", file=sys.stderr)
         sys.exit(2)
 
     cpu_pool = None
