@@ -52,6 +52,31 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def _record(workload, kind):
+    """Fields of profiles/<workload>_<kind>.txt, or None when there is no record
+    or it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{kind}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    return rec if rec.get("source_sha256") == kernel_source_hash() else None
+
+
+def valu_record(workload):
+    """VALU wave instructions per launch of the workload's dominant kernel, from
+    the counter record profiles/<workload>_valu.txt (SQ_INSTS_VALU), or None."""
+    rec = _record(workload, "valu")
+    try:
+        return int(rec["valu_wave_instructions_per_launch"]) if rec else None
+    except (KeyError, ValueError):
+        return None
+
+
 def traffic_record(workload):
     """HBM bytes per launch of the workload's dominant kernel, from the counter
     record profiles/<workload>_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled by
@@ -737,6 +762,16 @@ def main():
     if tr:
         roofline["traffic_read"] = tr["read"]
         roofline["traffic_write"] = tr["write"]
+    valu = valu_record(wl.workload_key)
+    if valu:
+        # Issue rate of vector instructions against the chip's: every CU issues at
+        # most one wave instruction per clock (4 SIMDs, a wave64 instruction each
+        # 4 clocks).
+        rate = valu / (k_ms * 1e-3) / 1e9
+        peak = N_CU * CLOCK_GHZ
+        roofline["valu_issue"] = {"achieved": round(rate, 1), "peak": round(peak, 1),
+                                  "unit": "G wave-instructions/s", "frac": round(rate / peak, 4),
+                                  "instructions_per_launch": valu}
 
     cpu = None
     if args.cpu_budget > 0:
