@@ -78,8 +78,11 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[i][j] = pixel(px, i, j) - (SEL == SEL_Q ? P.shift : 0);
+    for (int j = 0; j < 8; ++j) v[i][j] = pixel(px, i, j);
   pass2d<int, true>(v);
+  // The level shift only moves the DC term: row 0 of C0 is all ones and rows
+  // 1..7 sum to zero, so C0 (A - s) C0^T = C0 A C0^T - 64 s e_00.
+  if constexpr (SEL == SEL_Q) v[0][0] -= 64 * P.shift;
 
   // Selection: keep the first r zig-zag positions, or quantise all 64.
   const int n_kept = SEL == SEL_Q ? 64 : P.r;
@@ -91,14 +94,20 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
     });
   }
 
-  // Count pass, wave prefix, emit pass.
-  int cnt = 0;
+  // Nonzero kept values by zig-zag rank (bit rank of nz_lo / nz_hi), the count,
+  // a wave prefix, and the emit pass.  The emit walks the ranks in chunks of 8
+  // and skips a chunk that is zero in every lane of the wave (its 8 zeros only
+  // lengthen the run), which at ordinary qualities is most of them.
+  uint32_t nz_lo = 0, nz_hi = 0;
 #pragma unroll
   for (int rank = 0; rank < 64; ++rank) {
     const int kl = kZigZag.order[rank];
-    cnt += (rank < n_kept && v[kl >> 3][kl & 7] != 0) ? 1 : 0;
+    const uint32_t nz = (rank < n_kept) ? min((uint32_t)v[kl >> 3][kl & 7], 1u) : 0u;
+    if (rank < 32) nz_lo |= nz << rank;
+    else nz_hi |= nz << (rank - 32);
   }
-  if (!valid) cnt = 0;
+  if (!valid) nz_lo = nz_hi = 0;
+  const int cnt = __builtin_popcount(nz_lo) + __builtin_popcount(nz_hi);
   int off = cnt;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -107,22 +116,28 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
   }
   const int total = __shfl(off, 63, 64);
   off -= cnt;                                  // exclusive
-  if (valid) {
+  {
     int run = 0, k = off;
 #pragma unroll
-    for (int rank = 0; rank < 64; ++rank) {
-      const int kl = kZigZag.order[rank];
-      const int val = v[kl >> 3][kl & 7];
-      if (rank < n_kept) {
-        if (val != 0) {
-          wpairs[k++] = pair_word(run, val);
+    for (int c8 = 0; c8 < 8; ++c8) {
+      const uint32_t bits = ((c8 < 4 ? nz_lo : nz_hi) >> (8 * (c8 & 3))) & 0xffu;
+      if (__ballot(bits != 0) == 0) {
+        run += 8;
+        continue;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int rank = 8 * c8 + i;
+        const int kl = kZigZag.order[rank];
+        if ((bits >> i) & 1u) {
+          wpairs[k++] = pair_word(run, v[kl >> 3][kl & 7]);
           run = 0;
         } else {
           ++run;
         }
       }
     }
-    o.counts[t] = (uint16_t)cnt;
+    if (valid) o.counts[t] = (uint16_t)cnt;
   }
   wave_sync();
   int32_t* slot = o.slots + (int64_t)group * kSlot;
