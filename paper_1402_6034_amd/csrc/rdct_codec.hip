@@ -17,6 +17,9 @@ namespace rdct {
 
 constexpr int kGroup = 64;                 // blocks per group (one wave)
 constexpr int kSlot = kGroup * 64;         // pairs a group can hold
+// At most this many nonzero positions across a wave: reconstruct basis image by
+// basis image (about 40 additions each) instead of the full inverse.
+constexpr int kSparseRanks = 10;
 
 using CodecOut = CodecOutArgs;
 
@@ -108,6 +111,15 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
   }
   if (!valid) nz_lo = nz_hi = 0;
   const int cnt = __builtin_popcount(nz_lo) + __builtin_popcount(nz_hi);
+  // Ranks that are nonzero anywhere in the wave (wave-uniform).
+  uint32_t any_lo = nz_lo, any_hi = nz_hi;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    any_lo |= __shfl_xor(any_lo, d, 64);
+    any_hi |= __shfl_xor(any_hi, d, 64);
+  }
+  any_lo = __builtin_amdgcn_readfirstlane(any_lo);
+  any_hi = __builtin_amdgcn_readfirstlane(any_hi);
   int off = cnt;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -149,18 +161,46 @@ __global__ __launch_bounds__(256) void k_codec(Plane P, CodecOut o, QuantConsts 
   const bool al8 = ((reinterpret_cast<uintptr_t>(o.recon) | (uintptr_t)o.rpitch) & 7u) == 0;
   if constexpr (SEL == SEL_Q) {
     const QCPtr qc = codec_table();
-    double w[8][8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-#pragma unroll
-      for (int l = 0; l < 8; ++l) w[k][l] = (double)v[k][l] * qc->dq[k * 8 + l];
-    pass2d<double, false>(w);
     const double sh = (double)P.shift + 0.5;
+    double w[8][8];
+    if (__builtin_popcount(any_lo) + __builtin_popcount(any_hi) <= kSparseRanks) {
+      // Few positions are nonzero anywhere in the wave (the common case at
+      // ordinary qualities): add their basis images one by one.  Basis (k, l) is
+      // z C0[k][i] C0[l][j] with z = q Q s_k s_l and entries 0 or +-1, so each
+      // costs at most 64 additions, against ~450 operations for the full inverse.
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[i][j] = sh;
+      static_for<0, 64>([&](auto rc) {
+        constexpr int rank = decltype(rc)::value;
+        constexpr int kl = kZigZag.order[rank], k = kl >> 3, l = kl & 7;
+        if ((((rank < 32) ? any_lo : any_hi) >> (rank & 31)) & 1u) {
+          const double z = (double)v[k][l] * qc->dq[kl];
+          static_for<0, 64>([&](auto pc) {
+            constexpr int i = decltype(pc)::value >> 3, j = decltype(pc)::value & 7;
+            constexpr int sgn = kC0[k][i] * kC0[l][j];
+            if constexpr (sgn > 0) w[i][j] += z;
+            else if constexpr (sgn < 0) w[i][j] -= z;
+          });
+        }
+      });
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int l = 0; l < 8; ++l) w[k][l] = (double)v[k][l] * qc->dq[k * 8 + l];
+      pass2d<double, false>(w);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[i][j] += sh;
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       uint32_t b[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) b[j] = to_u8(w[i][j] + sh);
+      for (int j = 0; j < 8; ++j) b[j] = to_u8(w[i][j]);
       store_u8_row(P, o, x0, y0 + i, b, al8);
     }
   } else {

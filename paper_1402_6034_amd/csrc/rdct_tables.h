@@ -16,6 +16,25 @@ namespace rdct {
 
 // Diagonal of C0 C0^T.
 constexpr int kGram[8] = {8, 6, 4, 6, 8, 6, 4, 6};
+
+// C0 itself (Section 2), for code that needs single basis images rather than the
+// 22-addition flow graph.  Checked below: its rows are orthogonal with the Gram
+// diagonal above.
+constexpr int kC0[8][8] = {
+    {1, 1, 1, 1, 1, 1, 1, 1},      {1, 1, 1, 0, 0, -1, -1, -1},  {1, 0, 0, -1, -1, 0, 0, 1},
+    {1, 0, -1, -1, 1, 1, 0, -1},   {1, -1, -1, 1, 1, -1, -1, 1}, {1, -1, 0, 1, -1, 0, 1, -1},
+    {0, -1, 1, 0, 0, 1, -1, 0},    {0, -1, 1, -1, 1, -1, 1, 0}};
+
+constexpr bool c0_gram_ok() {
+  for (int k = 0; k < 8; ++k)
+    for (int l = 0; l < 8; ++l) {
+      int d = 0;
+      for (int j = 0; j < 8; ++j) d += kC0[k][j] * kC0[l][j];
+      if (d != (k == l ? kGram[k] : 0)) return false;
+    }
+  return true;
+}
+static_assert(c0_gram_ok(), "C0 rows must be orthogonal with norms g");
 // 24 / g_k: S^2 = diag(kDp) / 24, so the exact reconstruction numerator is
 // R = C0^T D' Y D' C0 with A' = R / 576.
 constexpr int kDp[8] = {3, 4, 6, 4, 3, 4, 6, 4};
