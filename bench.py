@@ -218,6 +218,10 @@ def seeded_planes(n, size, planes_cache=None):
     return imgs
 
 
+
+# rdct_layout_t of a batch plan's tuning.
+LAYOUT_NAME = {1: "strided", 2: "per-plane"}
+
 class RetentionSweep:
     """256 planes of 512 x 512, seeds 0..255: forward to int32 coefficients and
     the retention error of every plane for r = 1..45 (exact integer SSE from
@@ -236,7 +240,8 @@ class RetentionSweep:
         self.plan = R.BatchPlan(self.imgs, [self.sel] * n, R.COEF_I32, recon=False, r_count=45)
         if autotune:
             t = self.plan.autotune(reps=5)
-            log(f"[bench] autotuned: waves/wg {t.waves_per_wg}, wg/cu {t.wgs_per_cu}")
+            log(f"[bench] autotuned: {LAYOUT_NAME[t.layout]}, waves/wg {t.waves_per_wg}, "
+                f"wg/cu {t.wgs_per_cu}")
         self.nb1 = (size // 8) ** 2
         self.psnr = None
 
@@ -259,8 +264,10 @@ class RetentionSweep:
     def config(self):
         t = self.plan.tuning
         return {"workload": self.name, "planes": self.n, "plane": [self.size, self.size],
-                "r": [1, 45], "coef": "int32", "launches_per_step": 1, "waves_per_wg": t.waves_per_wg,
-                "wgs_per_cu": t.wgs_per_cu, "graph": bool(t.use_graph)}
+                "r": [1, 45], "coef": "int32", "layout": LAYOUT_NAME[t.layout],
+                "kernel_launches_per_step": 1 if t.layout == 2 else 2,
+                "waves_per_wg": t.waves_per_wg, "wgs_per_cu": t.wgs_per_cu,
+                "graph": bool(t.use_graph)}
 
     def plain(self, steps=3):
         """The same sweep as one rdct_compress_eval launch per plane."""
@@ -499,7 +506,8 @@ class RaggedBatch:
         log(f"[bench] plan: {self.nb} blocks in {self.plan.n_items} work items")
         if autotune:
             t = self.plan.autotune(reps=3)
-            log(f"[bench] tuned geometry: {t.waves_per_wg} waves/WG x {t.wgs_per_cu} WGs/CU")
+            log(f"[bench] tuned geometry: {LAYOUT_NAME[t.layout]}, {t.waves_per_wg} waves/WG x "
+                f"{t.wgs_per_cu} WGs/CU")
         self.px = sum(it.height * it.width for it in self.items)
         self.psnr = None
 
@@ -524,7 +532,8 @@ class RaggedBatch:
         t = self.plan.tuning
         return {"workload": self.name, "planes": len(self.items), "blocks": self.nb,
                 "pixels": self.px, "coef": "int16", "recon": "float32", "level_shift": 128,
-                "waves_per_wg": t.waves_per_wg, "wgs_per_cu": t.wgs_per_cu,
+                "layout": LAYOUT_NAME[t.layout], "waves_per_wg": t.waves_per_wg,
+                "wgs_per_cu": t.wgs_per_cu,
                 "graph": bool(t.use_graph)}
 
     def plain(self, steps=2):

@@ -169,11 +169,20 @@ typedef struct {
 } rdct_plane_desc_t;
 
 /* Launch geometry of the persistent kernel. */
+typedef enum {
+  RDCT_LAYOUT_DEFAULT = 0,    /* from the tuning cache, else STRIDED                  */
+  RDCT_LAYOUT_STRIDED = 1,    /* persistent workgroups stride over every plane's work
+                                 items; a clearing launch, then sums added atomically */
+  RDCT_LAYOUT_PER_PLANE = 2   /* one workgroup per plane, its waves striding over the
+                                 plane's items; sums stored, no clearing launch
+                                 (wgs_per_cu unused); suits many similar planes      */
+} rdct_layout_t;
+
 typedef struct {
   int32_t waves_per_wg;    /* 1, 2 or 4; 0 = from the tuning cache or default      */
   int32_t wgs_per_cu;      /* resident workgroups per compute unit, 1..16; 0 = same */
   int32_t use_graph;       /* 1: runs replay a captured hipGraph; 0: plain launches */
-  int32_t reserved;
+  int32_t layout;          /* rdct_layout_t                                         */
 } rdct_tuning_t;
 
 typedef struct rdct_batch_plan rdct_batch_plan_t;
@@ -213,10 +222,11 @@ rdct_status_t rdct_batch_plan_create_sweep(const rdct_plane_desc_t* planes, int3
                                            uint64_t* sse_out, const rdct_tuning_t* tuning,
                                            rdct_batch_plan_t** out);
 
-/* Run the plan on `stream` (asynchronous; no allocation): a launch that clears
-   sse_out, then the persistent kernel.  With use_graph the first run captures
-   the two launches into a hipGraph; later runs replay it.  Runs of one plan must
-   not overlap (on two streams at once): they share the plan's outputs. */
+/* Run the plan on `stream` (asynchronous; no allocation).  STRIDED layout: a
+   launch that clears sse_out, then the persistent kernel; PER_PLANE: one launch.
+   With use_graph the first run captures the launches into a hipGraph; later runs
+   replay it.  Runs of one plan must not overlap (on two streams at once): they
+   share the plan's outputs. */
 rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
 
 /* Blocks and work items of a plan, and the geometry it runs with (any pointer
@@ -224,10 +234,11 @@ rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
 rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
                                    int32_t* n_items, rdct_tuning_t* used);
 
-/* Time every candidate geometry on this plan (reps launches each, median of
-   HIP-event durations, synchronous), adopt the fastest, store it in the tuning
-   cache (file named by RDCT_TUNING_CACHE, default ~/.cache/rdct_tuning.json,
-   keyed by architecture, path variant and size class) and return it in *best. */
+/* Time every candidate geometry on this plan (both layouts; reps launches each,
+   median of HIP-event durations, synchronous), adopt the fastest, store it in
+   the tuning cache (file named by RDCT_TUNING_CACHE, default
+   ~/.cache/rdct_tuning.json, keyed by architecture, path variant, size class
+   and plane-count class) and return it in *best. */
 rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* stream,
                                   rdct_tuning_t* best);
 

@@ -1,10 +1,15 @@
 // Batch planner: many planes of uneven sizes in one persistent launch.
 //
 // A plan uploads, once, a device work list of 128-block items (plane, first
-// block), the per-plane descriptors and the distinct quantisation tables.  A
-// run zeroes the per-plane error sums with a small kernel and launches the
-// persistent kernel, whose waves stride over the work list; both launches can
-// be captured into a hipGraph and replayed.  Per-block arithmetic is the same
+// block) grouped by plane, each plane's first item, the per-plane descriptors
+// and the distinct quantisation tables.  Two layouts run the list:
+//  * strided: a run zeroes the per-plane error sums with a small kernel and
+//    launches the persistent kernel, whose waves stride over the whole list
+//    and add their sums atomically;
+//  * per plane: one workgroup per plane strides over that plane's items and
+//    stores its sums -- one launch, no atomics, but the largest plane bounds
+//    the run, so it suits batches of many similar planes.
+// A run's launches can be captured into a hipGraph and replayed.  Per-block arithmetic is the same
 // device code as the single-plane calls, so every plane's outputs are identical
 // whether it is processed alone or inside a batch.
 //
@@ -38,6 +43,7 @@ struct rdct_batch_plan {
   Plane* d_planes = nullptr;
   QuantConsts* d_tables = nullptr;
   WorkItem* d_items = nullptr;
+  int32_t* d_first = nullptr;  // plane b's items: d_first[b] .. d_first[b + 1] - 1
   rdct_tuning_t tuning{};
   int device = 0;
   int n_cu = 256;
@@ -61,6 +67,7 @@ void free_plan(rdct_batch_plan* p) {
   if (p->d_planes) (void)hipFree(p->d_planes);
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_first) (void)hipFree(p->d_first);
   delete p;
 }
 
@@ -71,6 +78,11 @@ int grid_of(const rdct_batch_plan* p, const rdct_tuning_t& t) {
 }
 
 hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t s) {
+  if (t.layout == RDCT_LAYOUT_PER_PLANE) {
+    if (p->n_items == 0) return launch_zero_u64(p->sse, (int64_t)p->n_planes * p->r_count, s);
+    return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables, p->d_items,
+                        p->n_items, p->n_planes, t.waves_per_wg, s, p->d_first);
+  }
   hipError_t e = launch_zero_u64(p->sse, (int64_t)p->n_planes * p->r_count, s);
   if (e != hipSuccess) return e;
   return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables,
@@ -100,16 +112,18 @@ rdct_status_t capture(rdct_batch_plan* p) {
 
 bool valid_tuning(const rdct_tuning_t& t) {
   return (t.waves_per_wg == 1 || t.waves_per_wg == 2 || t.waves_per_wg == 4) &&
-         t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16;
+         t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16 &&
+         (t.layout == RDCT_LAYOUT_STRIDED || t.layout == RDCT_LAYOUT_PER_PLANE);
 }
 
 std::string plan_key(const rdct_batch_plan* p) {
-  // Size class: log2 of the block count.
-  int cls = 0;
+  // Size classes: log2 of the block count and of the plane count.
+  int cls = 0, pcls = 0;
   for (int64_t b = p->n_blocks; b > 1; b >>= 1) ++cls;
+  for (int64_t b = p->n_planes; b > 1; b >>= 1) ++pcls;
   char buf[128];
-  snprintf(buf, sizeof(buf), "gfx950/batch/sel%d/co%d/recon%d/ev%d/log2blocks%d", p->sel, p->co,
-           p->recon ? 1 : 0, p->ev, cls);
+  snprintf(buf, sizeof(buf), "gfx950/batch/sel%d/co%d/recon%d/ev%d/log2blocks%d/log2planes%d",
+           p->sel, p->co, p->recon ? 1 : 0, p->ev, cls, pcls);
   return buf;
 }
 
@@ -139,6 +153,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   bool all_full = true;
   int64_t n_blocks = 0;
   std::vector<WorkItem> items;
+  std::vector<int32_t> first(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const rdct_plane_desc_t& d = planes[i];
     rdct_status_t st = check_plane(d.src, d.width, d.height, d.src_pitch, kMaxEvalBlocks);
@@ -181,10 +196,12 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     }
     if ((d.width % 8) != 0 || (d.height % 8) != 0) all_full = false;
     hp[i] = P;
+    first[i] = (int32_t)std::min<size_t>(items.size(), 0x7fffffff);
     for (int t0 = 0; t0 < P.nblocks; t0 += 128) items.push_back(WorkItem{i, t0});
     n_blocks += P.nblocks;
   }
   if (items.size() > (size_t)0x7fffffff) return RDCT_ERR_UNSUPPORTED;
+  first[n] = (int32_t)items.size();
   if (tables.empty()) {
     tables.emplace_back();
     memset(&tables[0], 0, sizeof(QuantConsts));
@@ -209,7 +226,9 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
 
   bool ok = hipMalloc(&p->d_planes, sizeof(Plane) * n) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(QuantConsts) * tables.size()) == hipSuccess &&
-            hipMalloc(&p->d_items, sizeof(WorkItem) * items.size()) == hipSuccess;
+            hipMalloc(&p->d_items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)) ==
+                hipSuccess &&
+            hipMalloc(&p->d_first, sizeof(int32_t) * (n + 1)) == hipSuccess;
   if (!ok) {
     free_plan(p);
     return RDCT_ERR_NO_MEMORY;
@@ -217,8 +236,10 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   ok = hipMemcpy(p->d_planes, hp.data(), sizeof(Plane) * n, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, tables.data(), sizeof(QuantConsts) * tables.size(),
                  hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(),
-                 hipMemcpyHostToDevice) == hipSuccess &&
+       (items.empty() || hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(),
+                                   hipMemcpyHostToDevice) == hipSuccess) &&
+       hipMemcpy(p->d_first, first.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice) ==
+           hipSuccess &&
        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     free_plan(p);
@@ -230,14 +251,17 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   t.waves_per_wg = 1;
   t.wgs_per_cu = 8;
   t.use_graph = 1;
+  t.layout = RDCT_LAYOUT_STRIDED;
   rdct_tuning_t cached;
   if (tune_cache_lookup(p->key, &cached)) {
     t.waves_per_wg = cached.waves_per_wg;
     t.wgs_per_cu = cached.wgs_per_cu;
+    t.layout = cached.layout;
   }
   if (tuning) {
     if (tuning->waves_per_wg) t.waves_per_wg = tuning->waves_per_wg;
     if (tuning->wgs_per_cu) t.wgs_per_cu = tuning->wgs_per_cu;
+    if (tuning->layout) t.layout = tuning->layout;
     t.use_graph = tuning->use_graph ? 1 : 0;
   }
   if (!valid_tuning(t)) {
@@ -293,43 +317,55 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RDCT_ERR_HIP;
-  const int wpgs[] = {1, 2, 4};
-  const int per_cu_waves[] = {2, 4, 8, 12, 16};
+  // Candidates: the strided layout over waves per workgroup x resident waves
+  // per CU, and the per-plane layout over waves per workgroup.
+  std::vector<rdct_tuning_t> cands;
+  for (int wpg : {1, 2, 4}) {
+    for (int waves : {2, 4, 8, 12, 16}) {
+      if (waves % wpg) continue;
+      rdct_tuning_t t = plan->tuning;
+      t.layout = RDCT_LAYOUT_STRIDED;
+      t.waves_per_wg = wpg;
+      t.wgs_per_cu = waves / wpg;
+      cands.push_back(t);
+    }
+    rdct_tuning_t t = plan->tuning;
+    t.layout = RDCT_LAYOUT_PER_PLANE;
+    t.waves_per_wg = wpg;
+    t.wgs_per_cu = 1;
+    cands.push_back(t);
+  }
   float best_us = 1e30f;
   rdct_tuning_t best_t = plan->tuning;
   rdct_status_t st = RDCT_OK;
-  for (int wpg : wpgs) {
-    for (int waves : per_cu_waves) {
-      if (waves % wpg) continue;
-      rdct_tuning_t t = plan->tuning;
-      t.waves_per_wg = wpg;
-      t.wgs_per_cu = waves / wpg;
-      if (!valid_tuning(t)) continue;
-      // One untimed launch, then `reps` timed ones.
-      if (launch_direct(plan, t, s) != hipSuccess) { st = RDCT_ERR_HIP; break; }
-      std::vector<float> us;
-      for (int r = 0; r < reps && st == RDCT_OK; ++r) {
-        if (hipEventRecord(e0, s) != hipSuccess || launch_direct(plan, t, s) != hipSuccess ||
-            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          st = RDCT_ERR_HIP;
-          break;
-        }
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          st = RDCT_ERR_HIP;
-          break;
-        }
-        us.push_back(ms * 1000.f);
+  for (const rdct_tuning_t& t : cands) {
+    if (!valid_tuning(t)) continue;
+    // One untimed launch, then `reps` timed ones.
+    if (launch_direct(plan, t, s) != hipSuccess) {
+      st = RDCT_ERR_HIP;
+      break;
+    }
+    std::vector<float> us;
+    for (int r = 0; r < reps && st == RDCT_OK; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess || launch_direct(plan, t, s) != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = RDCT_ERR_HIP;
+        break;
       }
-      if (st != RDCT_OK) break;
-      std::sort(us.begin(), us.end());
-      const float med = us[us.size() / 2];
-      if (med < best_us) {
-        best_us = med;
-        best_t = t;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = RDCT_ERR_HIP;
+        break;
       }
+      us.push_back(ms * 1000.f);
     }
     if (st != RDCT_OK) break;
+    std::sort(us.begin(), us.end());
+    const float med = us[us.size() / 2];
+    if (med < best_us) {
+      best_us = med;
+      best_t = t;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -122,12 +122,16 @@ hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t hei
                           const QuantConsts& qc, hipStream_t stream);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t stream);
 
-// Persistent batch launch over a work list.  `planes` and `tables` are device
-// arrays; `items` has n_items entries.
+// Batch launch over a work list.  `planes` and `tables` are device arrays;
+// `items` has n_items entries, grouped by plane.  first == nullptr: `grid`
+// persistent workgroups stride over the list and add the error sums atomically
+// (cleared beforehand).  Otherwise first[b] .. first[b + 1] - 1 are plane b's
+// items, grid is the plane count, and each workgroup stores its plane's sums.
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
                         const QuantConsts* tables,
                         const WorkItem* items, int32_t n_items, int32_t grid,
-                        int32_t waves_per_wg, hipStream_t stream);
+                        int32_t waves_per_wg, hipStream_t stream,
+                        const int32_t* first = nullptr);
 
 int device_cu_count();
 int default_waves_per_wg();

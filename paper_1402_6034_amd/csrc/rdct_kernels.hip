@@ -690,14 +690,35 @@ __global__ __launch_bounds__(256, 1) void k_plane_w(Plane P, QuantConsts /*qc*/)
   plane_kernel_body<SEL, CO, RECON, EV>(P, kernarg_table());
 }
 
-// Persistent batch kernel: workgroups stride over a device work list; each wave
-// takes items wave_id, wave_id + n_waves, ...  Every wave runs to the end of the
-// list, so the grid drains without any device-side queue.
+// Plain stores of one plane's error sums (the wave's lanes each hold a part;
+// see flush_sums): every sum of the plane is written, so no clearing is needed.
+template <int EV>
+__device__ __forceinline__ void store_sums(const Plane& P, uint64_t part, int lane) {
+  if constexpr (EV == EV_SPATIAL || EV == EV_COEF) {
+    const uint64_t s = wave_sum_u64(part);
+    if (lane == 0) *P.sse = s;
+  } else if constexpr (EV == EV_SWEEP) {
+    if (lane >= P.r && lane < P.r + P.r_count) P.sse[lane - P.r] = part;
+    // r = 64 keeps every coefficient: no lane holds it and its sum is zero.
+    if (lane == 0 && P.r + P.r_count > 64) P.sse[64 - P.r] = 0;
+  }
+}
+
+// Batch kernel over a device work list, in one of two forms.
+//  * Strided (first == nullptr): persistent workgroups; each wave takes items
+//    wave_id, wave_id + n_waves, ...  and every wave runs to the end of the
+//    list, so the grid drains without any device-side queue.  Error sums are
+//    added with atomics (the caller clears them first).
+//  * One workgroup per plane (first != nullptr; plane b's items are
+//    first[b] .. first[b + 1] - 1): the workgroup's waves stride over the
+//    plane's items, their sums meet in LDS, and one wave stores the plane's
+//    totals -- no atomics and no clearing launch.  Suits batches of many
+//    planes of similar size.
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
                                                   const WorkItem* __restrict__ items,
-                                                  int n_items) {
+                                                  int n_items, const int* __restrict__ first) {
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -706,6 +727,62 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
   uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
                    wave * wave_stage_bytes<SEL, CO, RECON, EV>();
   uint32_t* sweep = lds + wave * (64 * 65);
+
+  // Items it, it + stride, ... below end; part(plane, lane part) after each.
+  auto run_items = [&](int it, int stride, int end, auto&& part) {
+    if (it >= end) return;
+    if constexpr (Prefetch<SEL, RECON, EV>::value) {
+      WorkItem w = items[it];
+      Pixels cur;
+      chunk_load(planes[w.plane], w.t0, lane, cur);
+      for (;;) {
+        const int itn = it + stride;
+        const bool more = itn < end;
+        WorkItem wn = w;
+        Pixels nxt;
+        if (more) {
+          wn = items[itn];
+          chunk_load(planes[wn.plane], wn.t0, lane, nxt);
+        }
+        const Plane& P = planes[w.plane];
+        part(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
+                                                      sweep, stage));
+        if (!more) break;
+        cur = nxt;
+        w = wn;
+        it = itn;
+      }
+    } else {
+      for (; it < end; it += stride) {
+        const WorkItem w = items[it];
+        const Plane& P = planes[w.plane];
+        Pixels cur;
+        chunk_load(P, w.t0, lane, cur);
+        part(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
+                                                      sweep, stage));
+      }
+    }
+  };
+
+  if (first != nullptr) {
+    const int b = blockIdx.x;
+    uint64_t acc = 0;
+    run_items(first[b] + wave, wpg, first[b + 1], [&](int, uint64_t part) { acc += part; });
+    if constexpr (EV != EV_NONE) {
+      // After the stages: wpg x 64 lane parts.
+      uint64_t* red = reinterpret_cast<uint64_t*>(
+          lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0) + wpg * wave_stage_bytes<SEL, CO, RECON, EV>() / 4);
+      red[wave * 64 + lane] = acc;
+      __syncthreads();
+      if (wave == 0) {
+        uint64_t v = 0;
+        for (int w = 0; w < wpg; ++w) v += red[w * 64 + lane];
+        store_sums<EV>(planes[b], v, lane);
+      }
+    }
+    return;
+  }
+
   int it = blockIdx.x * wpg + wave;
   if (it >= n_items) return;
   // The wave's error parts accumulate while its items stay in one plane and are
@@ -713,7 +790,7 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
   // rather than one per item, all on the same address.
   uint64_t acc = 0;
   int acc_plane = items[it].plane;
-  auto account = [&](int plane, uint64_t part) {
+  run_items(it, n_waves, n_items, [&](int plane, uint64_t part) {
     if constexpr (EV != EV_NONE) {
       if (plane != acc_plane) {
         flush_sums<EV>(planes[acc_plane], acc, lane);
@@ -722,54 +799,24 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
       }
       acc += part;
     }
-  };
-  if constexpr (Prefetch<SEL, RECON, EV>::value) {
-    WorkItem w = items[it];
-    Pixels cur;
-    chunk_load(planes[w.plane], w.t0, lane, cur);
-    for (;;) {
-      const int itn = it + n_waves;
-      const bool more = itn < n_items;
-      WorkItem wn = w;
-      Pixels nxt;
-      if (more) {
-        wn = items[itn];
-        chunk_load(planes[wn.plane], wn.t0, lane, nxt);
-      }
-      const Plane& P = planes[w.plane];
-      account(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
-                                                       sweep, stage));
-      if (!more) break;
-      cur = nxt;
-      w = wn;
-      it = itn;
-    }
-  } else {
-    for (; it < n_items; it += n_waves) {
-      const WorkItem w = items[it];
-      const Plane& P = planes[w.plane];
-      Pixels cur;
-      chunk_load(P, w.t0, lane, cur);
-      account(w.plane, plane_chunk<SEL, CO, RECON, EV>(P, (QCPtr)(tables + P.table), cur, lane,
-                                                       sweep, stage));
-    }
-  }
+  });
   if constexpr (EV != EV_NONE) flush_sums<EV>(planes[acc_plane], acc, lane);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 2) void k_batch(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
-                                                  const WorkItem* __restrict__ items, int n_items) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items);
+                                                  const WorkItem* __restrict__ items, int n_items,
+                                                  const int* __restrict__ first) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ planes,
                                                     const QuantConsts* __restrict__ tables,
                                                     const WorkItem* __restrict__ items,
-                                                    int n_items) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items);
+                                                    int n_items, const int* __restrict__ first) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,16 +945,19 @@ static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg,
 
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
-                                 const WorkItem* items, int n_items,
+                                 const WorkItem* items, int n_items, const int* first,
                                  int grid, int wpg, hipStream_t s) {
+  static_assert(Stage<CO>::wave_bytes % 8 == 0 && kReconStageBytes % 8 == 0,
+                "stages keep the per-plane sums area 8-byte aligned");
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
-                     (size_t)wpg * wave_stage_bytes<SEL, CO, RECON, EV>();
+                     (size_t)wpg * wave_stage_bytes<SEL, CO, RECON, EV>() +
+                     (first != nullptr && EV != EV_NONE ? (size_t)wpg * 64 * 8 : 0);
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items);
+                       tables, items, n_items, first);
   else
     hipLaunchKernelGGL((k_batch<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items);
+                       tables, items, n_items, first);
   return hipGetLastError();
 }
 
@@ -955,9 +1005,10 @@ hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
 
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
                         const QuantConsts* tables, const WorkItem* items,
-                        int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s) {
+                        int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s,
+                        const int32_t* first) {
   if (n_items <= 0) return hipSuccess;
-  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, grid, wpg, s)
+  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, first, grid, wpg, s)
 }
 
 hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height, int32_t r,

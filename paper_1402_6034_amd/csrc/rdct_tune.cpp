@@ -20,6 +20,7 @@ namespace {
 struct Entry {
   int waves_per_wg = 0;
   int wgs_per_cu = 0;
+  int layout = 0;
   float us = 0.f;
 };
 
@@ -48,6 +49,7 @@ std::map<std::string, Entry> load(const std::string& path) {
     if (!scan_int(line, "waves_per_wg", &en.waves_per_wg) ||
         !scan_int(line, "wgs_per_cu", &en.wgs_per_cu))
       continue;
+    if (!scan_int(line, "layout", &en.layout)) en.layout = RDCT_LAYOUT_STRIDED;
     const size_t u = line.find("\"us\": ");
     if (u != std::string::npos) en.us = (float)atof(line.c_str() + u + 6);
     m[line.substr(b, e - b)] = en;
@@ -78,7 +80,7 @@ bool tune_cache_lookup(const std::string& key, rdct_tuning_t* out) {
   out->waves_per_wg = it->second.waves_per_wg;
   out->wgs_per_cu = it->second.wgs_per_cu;
   out->use_graph = 1;
-  out->reserved = 0;
+  out->layout = it->second.layout;
   return true;
 }
 
@@ -86,7 +88,7 @@ void tune_cache_store(const std::string& key, const rdct_tuning_t& t, float us) 
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string path = tune_cache_path();
   auto m = load(path);
-  m[key] = Entry{t.waves_per_wg, t.wgs_per_cu, us};
+  m[key] = Entry{t.waves_per_wg, t.wgs_per_cu, t.layout, us};
   mkdirs_for(path);
   const std::string tmp = path + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
@@ -94,9 +96,11 @@ void tune_cache_store(const std::string& key, const rdct_tuning_t& t, float us) 
   fprintf(f, "{\"rdct_tuning\": 1, \"entries\": [\n");
   size_t i = 0;
   for (const auto& kv : m) {
-    fprintf(f, "  {\"key\": \"%s\", \"waves_per_wg\": %d, \"wgs_per_cu\": %d, \"us\": %.3f}%s\n",
-            kv.first.c_str(), kv.second.waves_per_wg, kv.second.wgs_per_cu, kv.second.us,
-            ++i < m.size() ? "," : "");
+    fprintf(f,
+            "  {\"key\": \"%s\", \"waves_per_wg\": %d, \"wgs_per_cu\": %d, \"layout\": %d, "
+            "\"us\": %.3f}%s\n",
+            kv.first.c_str(), kv.second.waves_per_wg, kv.second.wgs_per_cu, kv.second.layout,
+            kv.second.us, ++i < m.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);

@@ -24,6 +24,7 @@ LIB_PATH = os.environ.get("RDCT_LIB") or os.path.join(_HERE, "librdct.so")
  ERR_CANCELLED) = range(9)
 # rdct_coef_t
 COEF_I32, COEF_I16, COEF_F32 = 0, 1, 2
+LAYOUT_DEFAULT, LAYOUT_STRIDED, LAYOUT_PER_PLANE = 0, 1, 2
 # rdct_sel_mode_t
 SEL_NONE, SEL_ZIGZAG, SEL_QUANT = 0, 1, 2
 
@@ -99,7 +100,7 @@ class PlaneDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """rdct_tuning_t."""
     _fields_ = [("waves_per_wg", c_int32), ("wgs_per_cu", c_int32), ("use_graph", c_int32),
-                ("reserved", c_int32)]
+                ("layout", c_int32)]
 
 
 class QualityDesc(ctypes.Structure):

@@ -1,5 +1,6 @@
 """Batch plans: each plane's result inside a ragged batch equals its result alone
-(bit-exact: same kernels, integer reductions), and equals the oracle; captured
+(bit-exact: same kernels, integer reductions), and equals the oracle, in both
+layouts (persistent strided workgroups, one workgroup per plane); captured
 graphs give the same result on every replay."""
 import numpy as np
 import pytest
@@ -12,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 R = pytest.importorskip("paper_1402_6034_amd.rdct")
 DEV = "cuda:0"
+LAYOUTS = [R.LAYOUT_STRIDED, R.LAYOUT_PER_PLANE]
 
 
 def host(t):
@@ -31,13 +33,16 @@ def ragged_planes(n, seed, full_blocks=True):
     return imgs, [torch.from_numpy(a).to(DEV) for a in imgs], rng
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("full", [True, False])
 @pytest.mark.parametrize("use_graph", [1, 0])
-def test_quant_batch_equals_single_and_oracle(full, use_graph):
+def test_quant_batch_equals_single_and_oracle(full, use_graph, layout):
     imgs, dev, rng = ragged_planes(23, 1, full)
     quals = [int(q) for q in rng.integers(10, 91, size=len(imgs))]
     sels = [R.select(R.SEL_QUANT, quality=q, level_shift=128) for q in quals]
-    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(1, 4, use_graph, 0))
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True,
+                       tuning=R.Tuning(1 + 3 * (layout == R.LAYOUT_PER_PLANE), 4, use_graph, layout))
+    assert plan.tuning.layout == layout
     plan.run()
     sse = host(plan.sse)
     for i, (img, d, sel) in enumerate(zip(imgs, dev, sels)):
@@ -54,11 +59,12 @@ def test_quant_batch_equals_single_and_oracle(full, use_graph):
     plan.close()
 
 
-def test_retention_batch_equals_single_and_oracle():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_retention_batch_equals_single_and_oracle(layout):
     imgs, dev, rng = ragged_planes(17, 2, full_blocks=False)
     rs = [int(r) for r in rng.integers(1, 46, size=len(imgs))]
     sels = [R.select(R.SEL_ZIGZAG, r=r) for r in rs]
-    plan = R.BatchPlan(dev, sels, R.COEF_I32, recon=True)
+    plan = R.BatchPlan(dev, sels, R.COEF_I32, recon=True, tuning=R.Tuning(2, 4, 1, layout))
     plan.run()
     sse = host(plan.sse)
     for i, (img, d, sel) in enumerate(zip(imgs, dev, sels)):
@@ -71,10 +77,11 @@ def test_retention_batch_equals_single_and_oracle():
     plan.close()
 
 
-def test_graph_replays_are_identical():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_graph_replays_are_identical(layout):
     imgs, dev, rng = ragged_planes(9, 3)
     sels = [R.select(R.SEL_QUANT, quality=int(q), level_shift=128) for q in rng.integers(10, 91, 9)]
-    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(1, 2, 1, 0))
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(1, 2, 1, layout))
     plan.run()
     ref = (host(plan.sse).copy(), host(plan.coef).copy(), host(plan.recon).copy())
     for k in range(4):
@@ -98,24 +105,26 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     plan.run()
     before = host(plan.sse).copy()
     t = plan.autotune(reps=2)
-    assert t.waves_per_wg in (1, 2, 4) and 1 <= t.wgs_per_cu <= 16
+    assert t.waves_per_wg in (1, 2, 4) and 1 <= t.wgs_per_cu <= 16 and t.layout in LAYOUTS
     plan.run()
     assert np.array_equal(host(plan.sse), before)
     text = (tmp_path / "tune.json").read_text()
-    assert '"waves_per_wg"' in text and "gfx950/batch" in text
+    assert '"waves_per_wg"' in text and '"layout"' in text and "gfx950/batch" in text
     # A new plan of the same class picks the cached geometry.
     plan2 = R.BatchPlan(dev, sels, R.COEF_I16, recon=True)
-    assert (plan2.tuning.waves_per_wg, plan2.tuning.wgs_per_cu) == (t.waves_per_wg, t.wgs_per_cu)
+    got = (plan2.tuning.waves_per_wg, plan2.tuning.wgs_per_cu, plan2.tuning.layout)
+    assert got == (t.waves_per_wg, t.wgs_per_cu, t.layout)
     plan.close()
     plan2.close()
 
 
-def test_batch_of_one_full_hd_plane_and_tiny_planes():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_of_one_full_hd_plane_and_tiny_planes(layout):
     shapes = [(1080, 1920), (8, 8), (1, 1), (13, 7)]
     imgs = [synth.render_np(50 + i, h, w) for i, (h, w) in enumerate(shapes)]
     dev = [torch.from_numpy(a).to(DEV) for a in imgs]
     sels = [R.select(R.SEL_ZIGZAG, r=r) for r in (10, 1, 64, 3)]
-    plan = R.BatchPlan(dev, sels, None, recon=False)
+    plan = R.BatchPlan(dev, sels, None, recon=False, tuning=R.Tuning(4, 2, 1, layout))
     plan.run()
     sse = host(plan.sse)
     for i, img in enumerate(imgs):
@@ -127,14 +136,17 @@ def test_batch_of_one_full_hd_plane_and_tiny_planes():
     plan.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("use_graph", [1, 0])
-def test_sweep_batch_equals_single_and_oracle(use_graph):
+def test_sweep_batch_equals_single_and_oracle(use_graph, layout):
     imgs, dev, rng = ragged_planes(19, 5)
     count = 12
     r0s = [int(r) for r in rng.integers(1, 64 - count + 2, size=len(imgs))]
+    r0s[3] = 64 - count + 1     # a range that ends at r = 64
     sels = [R.select(R.SEL_ZIGZAG, r=r) for r in r0s]
     plan = R.BatchPlan(dev, sels, R.COEF_I32, recon=True, r_count=count,
-                       tuning=R.Tuning(2, 4, use_graph, 0))
+                       tuning=R.Tuning(2, 4, use_graph, layout))
+    plan.sse.fill_(-1)          # every sum is written by a run
     for _ in range(2):          # twice: the sums are cleared by every run
         plan.run()
     sse = host(plan.sse)
@@ -144,7 +156,8 @@ def test_sweep_batch_equals_single_and_oracle(use_graph):
         assert np.array_equal(host(s1), sse[i]), i
         assert np.array_equal(host(c1), host(plan.coef_views[i])), i
         assert np.array_equal(host(r1), host(plan.recon_views[i])), i
-    for i in (0, 7, 18):
+    assert sse[3][-1] == 0
+    for i in (0, 3, 7, 18):
         rs = list(range(r0s[i], r0s[i] + count))
         ref = O.retention_eval(imgs[i], rs)
         assert [int(v) for v in sse[i]] == [ref["sse_num"][r] for r in rs], i
