@@ -187,17 +187,39 @@ class FrameQuant:
                           "forward + exact quantisation"}
 
 
-def read_back(dev, owner):
-    """The device tensor's values on the host, through a pinned buffer kept on
-    `owner` (an asynchronous copy on the current stream, then its completion)."""
-    import torch
-    buf = getattr(owner, "_pinned", None)
-    if buf is None or buf.shape != dev.shape or buf.dtype != dev.dtype:
-        buf = torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True)
-        owner._pinned = buf
-    buf.copy_(dev, non_blocking=True)
-    torch.cuda.current_stream().synchronize()
-    return buf.numpy()
+class SumsPipe:
+    """Read-back of a plan's error sums for steps run two deep.  submit(slot)
+    copies the sums into device buffer `slot` on the launch stream (a small
+    device-to-device copy), then a side stream copies that buffer into pinned
+    host buffer `slot`, so the transfer to the host overlaps the next step's
+    kernel; take(slot) waits for that transfer and returns the values."""
+
+    def __init__(self, dev):
+        import torch
+        self.dev = dev
+        self.stage = [torch.empty_like(dev) for _ in range(2)]
+        self.bufs = [torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True) for _ in range(2)]
+        self.side = torch.cuda.Stream()
+        self.staged = [torch.cuda.Event() for _ in range(2)]
+        self.copied = [torch.cuda.Event() for _ in range(2)]
+        self.used = [False, False]
+
+    def submit(self, slot):
+        import torch
+        main = torch.cuda.current_stream()
+        if self.used[slot]:
+            main.wait_event(self.copied[slot])     # the buffer's last transfer is done
+        self.stage[slot].copy_(self.dev)
+        self.staged[slot].record(main)
+        self.side.wait_event(self.staged[slot])
+        with torch.cuda.stream(self.side):
+            self.bufs[slot].copy_(self.stage[slot], non_blocking=True)
+            self.copied[slot].record(self.side)
+        self.used[slot] = True
+
+    def take(self, slot):
+        self.copied[slot].synchronize()
+        return self.bufs[slot].numpy()
 
 
 def seeded_planes(n, size, planes_cache=None):
@@ -250,13 +272,28 @@ class RetentionSweep:
 
     kernel_launch = launch
 
-    def step(self):
-        import numpy as np
+    def submit(self, slot):
+        """Enqueue one step: the plan run and the copy of its sums."""
+        if getattr(self, "pipe", None) is None:
+            self.pipe = SumsPipe(self.plan.sse)
         self.plan.run()
-        s = read_back(self.plan.sse, self).astype(np.float64) / 576.0 ** 2
-        mse = s / float(self.size * self.size)
+        self.pipe.submit(slot)
+
+    def finish(self, slot):
+        """Wait for the step in `slot` and turn its sums into PSNR."""
+        import numpy as np
+        # PSNR = 10 log10(255^2 / MSE), MSE = sum / 576^2 / pixels.
+        sse = self.pipe.take(slot)
+        if getattr(self, "psnr", None) is None or self.psnr.shape != sse.shape:
+            self.psnr = np.empty(sse.shape, dtype=np.float64)
         with np.errstate(divide="ignore"):
-            self.psnr = 10.0 * np.log10(255.0 ** 2 / mse)
+            np.divide(255.0 ** 2 * 576.0 ** 2 * float(self.size * self.size), sse, out=self.psnr)
+        np.log10(self.psnr, out=self.psnr)
+        self.psnr *= 10.0
+
+    def step(self):
+        self.submit(0)
+        self.finish(0)
 
     blocks_per_step = property(lambda self: self.n * self.nb1)
     bytes_per_block = 64 + 256
@@ -516,14 +553,30 @@ class RaggedBatch:
 
     kernel_launch = launch
 
-    def step(self):
-        import numpy as np
+    def submit(self, slot):
+        """Enqueue one step: the plan run and the copy of its sums."""
+        if getattr(self, "pipe", None) is None:
+            self.pipe = SumsPipe(self.plan.sse)
         self.plan.run()
-        s = read_back(self.plan.sse, self).astype(np.float64) * 2.0 ** -20
-        if getattr(self, "npx", None) is None:
-            self.npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
+        self.pipe.submit(slot)
+
+    def finish(self, slot):
+        """Wait for the step in `slot` and turn its sums into PSNR."""
+        import numpy as np
+        # PSNR = 10 log10(255^2 / MSE), MSE = sum * 2^-20 / pixels.
+        sse = self.pipe.take(slot)
+        if getattr(self, "psnr_num", None) is None:
+            npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
+            self.psnr_num = 255.0 ** 2 * 2.0 ** 20 * npx
+            self.psnr = np.empty(len(self.items), dtype=np.float64)
         with np.errstate(divide="ignore"):
-            self.psnr = 10.0 * np.log10(255.0 ** 2 / (s / self.npx))
+            np.divide(self.psnr_num, sse, out=self.psnr)
+        np.log10(self.psnr, out=self.psnr)
+        self.psnr *= 10.0
+
+    def step(self):
+        self.submit(0)
+        self.finish(0)
 
     blocks_per_step = property(lambda self: self.nb)
     bytes_per_block = 64 + 128 + 256
@@ -740,8 +793,18 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        wl.step()
+    if hasattr(wl, "submit"):
+        # Two steps in flight: step k + 1 is enqueued before step k's sums are
+        # read back and turned into PSNR, so host work overlaps the next kernel.
+        for k in range(args.steps):
+            wl.submit(k & 1)
+            if k:
+                wl.finish((k - 1) & 1)
+        if args.steps:
+            wl.finish((args.steps - 1) & 1)
+    else:
+        for _ in range(args.steps):
+            wl.step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt * 1e3 / args.steps

@@ -181,7 +181,8 @@ typedef enum {
 typedef struct {
   int32_t waves_per_wg;    /* 1, 2 or 4; 0 = from the tuning cache or default      */
   int32_t wgs_per_cu;      /* resident workgroups per compute unit, 1..16; 0 = same */
-  int32_t use_graph;       /* 1: runs replay a captured hipGraph; 0: plain launches */
+  int32_t use_graph;       /* 1: runs replay a captured hipGraph; 0: plain launches
+                              (the default with a NULL tuning: measured faster)      */
   int32_t layout;          /* rdct_layout_t                                         */
 } rdct_tuning_t;
 

@@ -253,16 +253,20 @@ __global__ __launch_bounds__(kScanChunk) void k_codec_scan(
   if (g < n_groups) local[g] = before + inc - v;
 }
 
-// One wave per group: the group's offset, its blocks' offsets and the copy of
-// its pairs.
-__global__ __launch_bounds__(64) void k_codec_pack(const uint16_t* __restrict__ counts,
+// One wave per group, kPackWaves groups per workgroup (64-thread workgroups
+// leave the run bound by workgroup dispatch): the group's offset, its blocks'
+// offsets and the copy of its pairs.
+constexpr int kPackWaves = 4;
+
+__global__ __launch_bounds__(64 * kPackWaves) void k_codec_pack(const uint16_t* __restrict__ counts,
                                                    const uint32_t* __restrict__ group_pairs,
                                                    const int32_t* __restrict__ slots,
                                                    const uint32_t* __restrict__ local,
                                                    int32_t n_groups, int32_t nblocks,
                                                    uint32_t* __restrict__ offsets,
                                                    int32_t* __restrict__ packed, int64_t capacity) {
-  const int g = blockIdx.x, lane = threadIdx.x;
+  const int g = blockIdx.x * kPackWaves + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (g >= n_groups) return;
   // Totals of the chunks before this group's (all of them full chunks).
   const int chunk = g / kScanChunk;
   uint32_t prev = 0;
@@ -312,7 +316,8 @@ hipError_t launch_codec_pack(const uint16_t* counts, const uint32_t* group_pairs
   if (groups <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_codec_scan, dim3((groups + kScanChunk - 1) / kScanChunk),
                      dim3(kScanChunk), 0, s, group_pairs, groups, workspace);
-  hipLaunchKernelGGL(k_codec_pack, dim3(groups), dim3(64), 0, s, counts, group_pairs, slots,
+  hipLaunchKernelGGL(k_codec_pack, dim3((groups + kPackWaves - 1) / kPackWaves),
+                     dim3(64 * kPackWaves), 0, s, counts, group_pairs, slots,
                      workspace, groups, nblocks, offsets, packed, capacity);
   return hipGetLastError();
 }

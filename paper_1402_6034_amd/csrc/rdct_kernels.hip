@@ -624,14 +624,21 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
   }
 }
 
-// Register budget: two waves per SIMD, except the quantisation variants that
-// keep pixels live for a pixel-domain error (planes with partial blocks) or
-// stage int32 coefficients beside the reconstruction; those get a full
-// wave-per-SIMD budget instead of spilling.
+// Register budget: two waves per SIMD, except the variants that would spill
+// heavily at that budget and get a full wave-per-SIMD budget instead:
+// quantisation keeping pixels live for a pixel-domain error (planes with
+// partial blocks) or staging int32 coefficients beside the reconstruction, and
+// retention writing 32-bit coefficients beside the reconstruction (8192^2,
+// r = 10: 154 -> 141 us with int32, 159 -> 142 us with float32; with the
+// 45-value sweep 198 -> 147 and 209 -> 150 us).  Retention variants spilling
+// less (32-bit coefficients without reconstruction, 16-bit with it) measured
+// the same either way and keep two waves per SIMD.
 template <int SEL, int CO, bool RECON, int EV>
 struct WideRegs {
   static constexpr bool value =
-      (SEL == SEL_Q) && (EV == EV_SPATIAL || (RECON && CO == CO_I32));
+      ((SEL == SEL_Q) && (EV == EV_SPATIAL || (RECON && CO == CO_I32))) ||
+      ((SEL == SEL_ZZ) && RECON && (CO == CO_I32 || CO == CO_F32) &&
+       (EV == EV_SPATIAL || EV == EV_SWEEP));
 };
 
 // Persistent batch kernels: prefetching the next work item costs ~40 registers;

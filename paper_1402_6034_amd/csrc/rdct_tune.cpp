@@ -79,7 +79,7 @@ bool tune_cache_lookup(const std::string& key, rdct_tuning_t* out) {
   if (it == m.end()) return false;
   out->waves_per_wg = it->second.waves_per_wg;
   out->wgs_per_cu = it->second.wgs_per_cu;
-  out->use_graph = 1;
+  out->use_graph = 0;
   out->layout = it->second.layout;
   return true;
 }
