@@ -32,21 +32,24 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Sources whose change invalidates a stored HBM-traffic record (the kernels,
 # their launch code and the build flags).
-KERNEL_SOURCES = ("paper_1402_6034_amd/csrc/rdct_kernels.hip",
-                  "paper_1402_6034_amd/csrc/rdct_quality.hip",
-                  "paper_1402_6034_amd/csrc/rdct_codec.hip",
-                  "paper_1402_6034_amd/csrc/rdct_device.h",
-                  "paper_1402_6034_amd/csrc/rdct_transforms.cpp",
-                  "paper_1402_6034_amd/csrc/rdct_internal.h",
-                  "paper_1402_6034_amd/csrc/rdct_tables.h",
-                  "paper_1402_6034_amd/csrc/rdct_api.cpp",
-                  "paper_1402_6034_amd/csrc/rdct_batch.cpp",
-                  "paper_1402_6034_amd/build.py")
+# Sources that decide each workload's dominant kernel and its launch: a profile
+# record counts only while the hash of its workload's files is unchanged.
+_CSRC = "paper_1402_6034_amd/csrc/"
+_COMMON = (_CSRC + "rdct_internal.h", _CSRC + "rdct_tables.h", "include/rdct.h",
+           "paper_1402_6034_amd/build.py")
+KERNEL_SOURCES = {
+    "ragged": (_CSRC + "rdct_kernels.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_batch.cpp"),
+    "sweep": (_CSRC + "rdct_kernels.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_batch.cpp"),
+    "frame": (_CSRC + "rdct_kernels.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_api.cpp"),
+    "quality": (_CSRC + "rdct_quality.hip", _CSRC + "rdct_quality_api.cpp",
+                _CSRC + "rdct_transforms.cpp"),
+    "codec": (_CSRC + "rdct_codec.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_codec_api.cpp"),
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(workload):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[workload] + _COMMON:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -64,7 +67,7 @@ def _record(workload, kind):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    return rec if rec.get("source_sha256") == kernel_source_hash() else None
+    return rec if rec.get("source_sha256") == kernel_source_hash(workload) else None
 
 
 def valu_record(workload):
@@ -91,7 +94,7 @@ def traffic_record(workload):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    if rec.get("source_sha256") != kernel_source_hash():
+    if rec.get("source_sha256") != kernel_source_hash(workload):
         return None
     try:
         return {"bytes": int(rec["traffic_bytes_per_launch"]),
@@ -823,7 +826,7 @@ def main():
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                     "traffic": tr["bytes"] if tr else None,
                     "kernel_ms": round(k_ms, 5), "flops_per_launch": flops,
-                    "kernel_source_sha256": kernel_source_hash()}
+                    "kernel_source_sha256": kernel_source_hash(wl.workload_key)}
     else:
         nb = wl.blocks_per_step
         alg_bytes = int(round(nb * wl.bytes_per_block))
@@ -832,7 +835,7 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tr["bytes"] if tr else None,
                     "kernel_ms": round(k_ms, 5), "bytes_per_launch": alg_bytes,
-                    "kernel_source_sha256": kernel_source_hash()}
+                    "kernel_source_sha256": kernel_source_hash(wl.workload_key)}
     if tr:
         roofline["traffic_read"] = tr["read"]
         roofline["traffic_write"] = tr["write"]
