@@ -90,12 +90,13 @@ def ragged():
     return items, imgs, sels
 
 
-@pytest.mark.parametrize("autotune", [False, True])
-def test_ragged_batch_sampled(ragged, autotune, tmp_path, monkeypatch):
+@pytest.mark.parametrize("mode", ["default", "autotune", "per-plane"])
+def test_ragged_batch_sampled(ragged, mode, tmp_path, monkeypatch):
     monkeypatch.setenv("RDCT_TUNING_CACHE", str(tmp_path / "tune.json"))
     items, imgs, sels = ragged
-    plan = R.BatchPlan(imgs, sels, R.COEF_I16, recon=True)
-    if autotune:
+    tuning = R.Tuning(4, 1, 0, R.LAYOUT_PER_PLANE) if mode == "per-plane" else None
+    plan = R.BatchPlan(imgs, sels, R.COEF_I16, recon=True, tuning=tuning)
+    if mode == "autotune":
         plan.autotune(reps=2)
     plan.run()
     sse = host(plan.sse)
@@ -134,10 +135,16 @@ def test_sweep_planes_full():
         assert [int(v) for v in host(sse)] == [ref["sse_num"][r] for r in range(1, 46)]
 
 
-def test_sweep_batched_full():
+@pytest.mark.parametrize("layout", ["strided", "per-plane"])
+def test_sweep_batched_full(layout):
+    """The sweep as the bench runs it (int32 coefficients, one launch; the
+    per-plane layout with four waves per workgroup is what the autotuner picks)."""
     imgs = [synth.render(s, 512, 512, device=DEV) for s in range(256)]
     sel = R.select(R.SEL_ZIGZAG, r=1)
-    plan = R.BatchPlan(imgs, [sel] * 256, None, recon=False, r_count=45)
+    tuning = R.Tuning(1, 4, 0, R.LAYOUT_STRIDED) if layout == "strided" else \
+        R.Tuning(4, 1, 0, R.LAYOUT_PER_PLANE)
+    plan = R.BatchPlan(imgs, [sel] * 256, R.COEF_I32, recon=False, r_count=45, tuning=tuning)
+    plan.sse.fill_(-1)
     plan.run()
     sse = host(plan.sse)
     for s in range(256):
@@ -146,6 +153,12 @@ def test_sweep_batched_full():
     for s in (3, 128):
         ref = O.retention_eval(host(imgs[s]), range(1, 46))
         assert [int(v) for v in sse[s]] == [ref["sse_num"][r] for r in range(1, 46)], s
+    rng = np.random.default_rng(11)
+    for s in (0, 77, 255):
+        idx = sample_idx(rng, 4096, 24)
+        want = O.forward_blocks(O.sample_blocks(host(imgs[s]), idx), 0) * O.retention_mask(1)
+        got = host(plan.coef_views[s][torch.from_numpy(idx).to(DEV)]).astype(np.int64)
+        assert np.array_equal(got, want.reshape(-1, 64)), s
     plan.close()
 
 
@@ -164,10 +177,13 @@ def test_frame_error_sums_split_into_bands(frame, mode):
     bands = sum(host(R.compress_eval(img[k * 2048:(k + 1) * 2048], sel, count)[0]).astype(np.int64)
                 for k in range(4))
     assert np.array_equal(whole, bands)
-    plan = R.BatchPlan([img], [sel], None, recon=False, r_count=count)
-    plan.run()
-    assert np.array_equal(host(plan.sse).reshape(-1).astype(np.int64), whole)
-    plan.close()
+    for lay in (R.LAYOUT_STRIDED, R.LAYOUT_PER_PLANE):
+        # Per plane: one workgroup takes all 8192 items of the frame.
+        plan = R.BatchPlan([img], [sel], None, recon=False, r_count=count,
+                           tuning=R.Tuning(4, 2, 0, lay))
+        plan.run()
+        assert np.array_equal(host(plan.sse).reshape(-1).astype(np.int64), whole), lay
+        plan.close()
     if mode == "sweep":
         assert np.all(np.diff(whole) <= 0)          # dropping fewer coefficients never adds error
 
