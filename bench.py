@@ -744,8 +744,8 @@ def _oracle_threads():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ragged", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
     ap.add_argument("--no-autotune", action="store_true",

@@ -235,8 +235,9 @@ rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
 rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
                                    int32_t* n_items, rdct_tuning_t* used);
 
-/* Time every candidate geometry on this plan (both layouts; reps launches each,
-   median of HIP-event durations, synchronous), adopt the fastest, store it in
+/* Time every candidate geometry on this plan (both layouts; three rounds of reps
+   back-to-back launches each, timed with HIP events, the median round's average;
+   synchronous), adopt the fastest, store it in
    the tuning cache (file named by RDCT_TUNING_CACHE, default
    ~/.cache/rdct_tuning.json, keyed by architecture, path variant, size class
    and plane-count class) and return it in *best. */
