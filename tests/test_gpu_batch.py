@@ -170,3 +170,52 @@ def test_sweep_batch_rejects_partial_blocks():
     sels = [R.select(R.SEL_ZIGZAG, r=1) for _ in dev]
     with pytest.raises(R.RdctError):
         R.BatchPlan(dev, sels, None, r_count=45)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_many_tiny_planes(layout):
+    """2000 planes of 1..24 pixels a side (one to nine blocks, partial blocks
+    included): every plane's sum equals its own launch and, for a sample, the
+    oracle; in the per-plane layout that is 2000 workgroups of one item each."""
+    rng = np.random.default_rng(77)
+    shapes = [(int(rng.integers(1, 25)), int(rng.integers(1, 25))) for _ in range(2000)]
+    imgs = [synth.render_np(9000 + i, h, w) for i, (h, w) in enumerate(shapes)]
+    dev = [torch.from_numpy(a).to(DEV) for a in imgs]
+    quals = [int(q) for q in rng.integers(5, 96, size=len(imgs))]
+    sels = [R.select(R.SEL_QUANT, quality=q, level_shift=128) for q in quals]
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True, tuning=R.Tuning(4, 4, 0, layout))
+    plan.sse.fill_(-1)
+    plan.run()
+    sse = host(plan.sse)
+    for i in rng.choice(len(imgs), size=60, replace=False):
+        s1, c1, r1 = R.compress_eval(dev[i], sels[i], 1, R.COEF_I16, True)
+        assert int(host(s1)[0]) == int(sse[i]), i
+        assert np.array_equal(host(c1), host(plan.coef_views[i])), i
+        assert np.array_equal(host(r1), host(plan.recon_views[i])), i
+    for i in range(0, len(imgs), 97):
+        ref = O.quant_eval(imgs[i], O.quant_table(quals[i]), level_shift=128)
+        assert np.array_equal(host(plan.coef_views[i]).astype(np.int64), ref["q"].reshape(-1, 64)), i
+        assert np.max(np.abs(host(plan.recon_views[i]) - ref["recon"])) <= 1e-4, i
+    plan.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_many_small_sweep_planes(layout):
+    """1500 whole-block planes of 8..32 pixels a side, retention sweep over the
+    full r = 20..64 range in one launch, against the oracle for a sample."""
+    rng = np.random.default_rng(78)
+    shapes = [(8 * int(rng.integers(1, 5)), 8 * int(rng.integers(1, 5))) for _ in range(1500)]
+    imgs = [synth.render_np(12000 + i, h, w) for i, (h, w) in enumerate(shapes)]
+    dev = [torch.from_numpy(a).to(DEV) for a in imgs]
+    count = 45
+    sels = [R.select(R.SEL_ZIGZAG, r=20)] * len(imgs)
+    plan = R.BatchPlan(dev, sels, None, recon=False, r_count=count,
+                       tuning=R.Tuning(2, 8, 0, layout))
+    plan.sse.fill_(-1)
+    plan.run()
+    sse = host(plan.sse)
+    assert np.all(sse[:, -1] == 0)                      # r = 64 keeps everything
+    for i in range(0, len(imgs), 53):
+        ref = O.retention_eval(imgs[i], range(20, 65))
+        assert [int(v) for v in sse[i]] == [ref["sse_num"][r] for r in range(20, 65)], i
+    plan.close()
