@@ -224,6 +224,35 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   }
   p->key = plan_key(p);
 
+  // Geometry, decided before anything is allocated: explicit fields > tuning
+  // cache > default.  A cache entry that is not a valid geometry is ignored.
+  rdct_tuning_t t{};
+  t.waves_per_wg = 1;
+  t.wgs_per_cu = 8;
+  // Plain launches by default: replaying a graph measured slower here (70.4 against
+  // 64.7 us per run of the 256-plane sweep), and a replay followed by a copy to
+  // the host on the same stream stalled (537 against 81 us per run and copy).
+  t.use_graph = 0;
+  t.layout = RDCT_LAYOUT_STRIDED;
+  rdct_tuning_t cached;
+  if (tune_cache_lookup(p->key, &cached)) {
+    rdct_tuning_t c = t;
+    c.waves_per_wg = cached.waves_per_wg;
+    c.wgs_per_cu = cached.wgs_per_cu;
+    c.layout = cached.layout;
+    if (valid_tuning(c)) t = c;
+  }
+  if (tuning) {
+    if (tuning->waves_per_wg) t.waves_per_wg = tuning->waves_per_wg;
+    if (tuning->wgs_per_cu) t.wgs_per_cu = tuning->wgs_per_cu;
+    if (tuning->layout) t.layout = tuning->layout;
+    t.use_graph = tuning->use_graph ? 1 : 0;
+  }
+  if (!valid_tuning(t)) {
+    delete p;
+    return RDCT_ERR_INVALID_ARG;
+  }
+
   bool ok = hipMalloc(&p->d_planes, sizeof(Plane) * n) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(QuantConsts) * tables.size()) == hipSuccess &&
             hipMalloc(&p->d_items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)) ==
@@ -246,31 +275,6 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     return RDCT_ERR_HIP;
   }
 
-  // Geometry: explicit > tuning cache > default.
-  rdct_tuning_t t{};
-  t.waves_per_wg = 1;
-  t.wgs_per_cu = 8;
-  // Plain launches by default: replaying a graph measured slower here (70.4 against
-  // 64.7 us per run of the 256-plane sweep), and a replay followed by a copy to
-  // the host on the same stream stalled (537 against 81 us per run and copy).
-  t.use_graph = 0;
-  t.layout = RDCT_LAYOUT_STRIDED;
-  rdct_tuning_t cached;
-  if (tune_cache_lookup(p->key, &cached)) {
-    t.waves_per_wg = cached.waves_per_wg;
-    t.wgs_per_cu = cached.wgs_per_cu;
-    t.layout = cached.layout;
-  }
-  if (tuning) {
-    if (tuning->waves_per_wg) t.waves_per_wg = tuning->waves_per_wg;
-    if (tuning->wgs_per_cu) t.wgs_per_cu = tuning->wgs_per_cu;
-    if (tuning->layout) t.layout = tuning->layout;
-    t.use_graph = tuning->use_graph ? 1 : 0;
-  }
-  if (!valid_tuning(t)) {
-    free_plan(p);
-    return RDCT_ERR_INVALID_ARG;
-  }
   p->tuning = t;
   *out = p;
   return RDCT_OK;

@@ -2,6 +2,8 @@
 (bit-exact: same kernels, integer reductions), and equals the oracle, in both
 layouts (persistent strided workgroups, one workgroup per plane); captured
 graphs give the same result on every replay."""
+import re
+
 import numpy as np
 import pytest
 import torch
@@ -219,3 +221,36 @@ def test_many_small_sweep_planes(layout):
         ref = O.retention_eval(imgs[i], range(20, 65))
         assert [int(v) for v in sse[i]] == [ref["sse_num"][r] for r in range(20, 65)], i
     plan.close()
+
+
+@pytest.mark.parametrize("tuning", [(3, 4, 0, 1), (1, 17, 0, 1), (1, 4, 0, 3), (2, 0, 0, -1)])
+def test_invalid_tuning_rejected(tuning):
+    """Waves per workgroup outside 1, 2, 4, resident workgroups outside 1..16 and
+    unknown layouts are refused at plan creation (nothing is launched)."""
+    imgs, dev, _ = ragged_planes(2, 8)
+    sels = [R.select(R.SEL_ZIGZAG, r=5)] * 2
+    with pytest.raises(R.RdctError) as e:
+        R.BatchPlan(dev, sels, None, tuning=R.Tuning(*tuning))
+    assert e.value.status == R.ERR_INVALID_ARG
+
+
+def test_invalid_cache_entry_is_ignored(tmp_path, monkeypatch):
+    """A tuning-cache entry that is not a valid geometry (edited by hand, or from
+    another build) is skipped: the plan takes the default geometry."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("RDCT_TUNING_CACHE", str(cache))
+    imgs, dev, _ = ragged_planes(6, 9)
+    sels = [R.select(R.SEL_QUANT, quality=50, level_shift=128)] * len(dev)
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True)
+    plan.autotune(reps=1)
+    plan.run()
+    want = host(plan.sse).copy()
+    plan.close()
+    text = cache.read_text()
+    cache.write_text(re.sub(r'"waves_per_wg": \d+', '"waves_per_wg": 3', text))
+    plan2 = R.BatchPlan(dev, sels, R.COEF_I16, recon=True)
+    t = plan2.tuning
+    assert (t.waves_per_wg, t.wgs_per_cu, t.layout, t.use_graph) == (1, 8, R.LAYOUT_STRIDED, 0)
+    plan2.run()
+    assert np.array_equal(host(plan2.sse), want)
+    plan2.close()
