@@ -764,6 +764,8 @@ def main():
                     help="after the run, copy MIB mebibytes device-to-device 3 times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be at least 1 and --warmup at least 0")
     if args.serve_requests is None:
         args.serve_requests = 4000 if args.workload == "ragged" else 0
     if args.gpus != 1:
@@ -805,8 +807,7 @@ def main():
             wl.submit(k & 1)
             if k:
                 wl.finish((k - 1) & 1)
-        if args.steps:
-            wl.finish((args.steps - 1) & 1)
+        wl.finish((args.steps - 1) & 1)
     else:
         for _ in range(args.steps):
             wl.step()
