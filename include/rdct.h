@@ -168,7 +168,7 @@ typedef struct {
   int64_t recon_pitch;     /* floats per reconstruction row                       */
 } rdct_plane_desc_t;
 
-/* Launch geometry of the persistent kernel. */
+/* Launch geometry of a batch plan. */
 typedef enum {
   RDCT_LAYOUT_DEFAULT = 0,    /* from the tuning cache, else STRIDED                  */
   RDCT_LAYOUT_STRIDED = 1,    /* persistent workgroups stride over every plane's work
@@ -196,8 +196,10 @@ typedef struct rdct_batch_plan rdct_batch_plan_t;
  * kernels, identical per-block results): coefficients, reconstruction and
  * sse_out[i] (units of rdct_sse_unit(mode)), overwritten.
  * Allocates device memory (the plan's tables) -- not a hot call.
- * tuning: NULL = tuning cache or defaults.
- * Errors: INVALID_ARG (any plane invalid, mixed modes or output nullness),
+ * tuning: NULL = tuning cache or defaults (a cache entry that is not a valid
+ * geometry is ignored); zero fields of a given tuning take the same sources.
+ * Errors: INVALID_ARG (any plane invalid, mixed modes or output nullness, a
+ * tuning field out of range -- checked before anything is allocated),
  * UNSUPPORTED, NO_MEMORY, HIP.
  */
 rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
