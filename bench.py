@@ -30,10 +30,8 @@ ALU_PEAK_TOPS = N_CU * 64 * CLOCK_GHZ / 1000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-# Sources whose change invalidates a stored HBM-traffic record (the kernels,
-# their launch code and the build flags).
 # Sources that decide each workload's dominant kernel and its launch: a profile
-# record counts only while the hash of its workload's files is unchanged.
+# record counts only while the code of its workload's files is unchanged.
 _CSRC = "paper_1402_6034_amd/csrc/"
 _COMMON = (_CSRC + "rdct_internal.h", _CSRC + "rdct_tables.h", "include/rdct.h",
            "paper_1402_6034_amd/build.py")
@@ -47,11 +45,37 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text):
+    """C/C++ source without comments and blank lines, so that editing a comment
+    leaves a record standing (string and character literals are kept whole)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = ("".join(out)).split("\n")
+    return "\n".join(ln.rstrip() for ln in lines if ln.strip())
+
+
 def kernel_source_hash(workload):
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES[workload] + _COMMON:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        h.update((text if rel.endswith(".py") else _code_only(text)).encode())
     return h.hexdigest()
 
 
