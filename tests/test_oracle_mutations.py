@@ -167,3 +167,29 @@ def test_half_even_pixel_rounding_is_caught(monkeypatch):
         return np.clip(np.rint(np.asarray(r_num) / 576.0), 0, 255).astype(np.uint8)
     monkeypatch.setattr(O, "u8_from_numerator", bad)
     _fails(CP.test_u8_rounding_is_half_away_and_clamped)
+
+
+def test_transposed_table_in_dequantize_is_caught(monkeypatch):
+    def bad(q, qtab):
+        return np.asarray(q, dtype=np.float64) * np.asarray(qtab, dtype=np.float64).T
+    monkeypatch.setattr(R, "dequantize", bad)
+    monkeypatch.setattr(O, "dequantize", bad)
+    _fails(P.test_quant_reconstruction_matches_loops)
+
+
+def test_dropped_rounding_term_in_quant_table_is_caught(monkeypatch):
+    def bad(quality):
+        f = 5000 // quality if quality < 50 else 200 - 2 * quality
+        return np.clip((R.JPEG_LUMA_Q50 * f) // 100, 1, 255).astype(np.int64)
+    monkeypatch.setattr(R, "quant_table", bad)
+    monkeypatch.setattr(O, "quant_table", bad)
+    _fails(P.test_quant_table_matches_libjpeg_at_every_quality)
+
+
+def test_float_quality_factor_in_quant_table_is_caught(monkeypatch):
+    def bad(quality):
+        f = 5000 / quality if quality < 50 else 200 - 2 * quality
+        return np.clip(np.floor((R.JPEG_LUMA_Q50 * f + 50) / 100), 1, 255).astype(np.int64)
+    monkeypatch.setattr(R, "quant_table", bad)
+    monkeypatch.setattr(O, "quant_table", bad)
+    _fails(P.test_quant_table_matches_libjpeg_at_every_quality)

@@ -253,9 +253,25 @@ def test_quant_table_golden_and_scaling():
         if prev is not None:
             assert np.all(t <= prev)
         prev = t
-    # IJG rule spot values: quality 75 -> f = 50, quality 25 -> f = 200.
-    assert np.array_equal(O.quant_table(75), np.clip((q50 * 50 + 50) // 100, 1, 255))
-    assert np.array_equal(O.quant_table(25), np.clip((q50 * 200 + 50) // 100, 1, 255))
+
+
+def _libjpeg_luma_table(quality):
+    """The luminance table libjpeg writes at `quality`: a 16 x 16 grey image saved
+    through Pillow at that quality and read back (natural order, k = row)."""
+    import io
+    from PIL import Image
+    buf = io.BytesIO()
+    Image.fromarray(np.zeros((16, 16), dtype=np.uint8)).save(buf, "JPEG", quality=quality)
+    buf.seek(0)
+    return np.array(Image.open(buf).quantization[0], dtype=np.int64).reshape(8, 8)
+
+
+def test_quant_table_matches_libjpeg_at_every_quality():
+    # The IJG quality rule as libjpeg implements it (an independent program):
+    # its rounding term, the integer 5000 / q and the clamps all show somewhere
+    # in 1..100, where quality 50 alone would not reveal them.
+    for q in range(1, 101):
+        assert np.array_equal(O.quant_table(q), _libjpeg_luma_table(q)), f"quality {q}"
 
 
 def _exact_round_half_away(y, q, gkk, gll):
@@ -428,3 +444,33 @@ def test_quant_pipeline_matches_loops():
                 y = int(res["Y"][0, bx, k, l])
                 assert abs(z - y / math.sqrt(g[k] * g[l])) < 1e-9
                 assert res["q"][0, bx, k, l] == _exact_round_half_away(y, int(qt[k, l]), g[k], g[l])
+
+
+def test_quant_reconstruction_matches_loops():
+    # The dequantised reconstruction A' = C_orth^T (q . Q) C_orth + 128 and its
+    # SSE, by pure-python loops over k, l, i, j, at tables that are not symmetric
+    # (a transposed table or a transposed inverse changes the result), plus the
+    # quantiser's bound |Z - q Q| <= Q / 2 per coefficient.
+    img = RNG.integers(0, 256, size=(16, 24)).astype(np.uint8)
+    t = O.approx_dct().tolist()
+    for quality in (50, 23, 81):
+        qt = O.quant_table(quality)
+        assert not np.array_equal(qt, qt.T)
+        res = O.quant_eval(img, qt)
+        sse = 0.0
+        for by in range(2):
+            for bx in range(3):
+                a = [[int(img[8 * by + i][8 * bx + j]) for j in range(8)] for i in range(8)]
+                q = res["q"][by, bx].tolist()
+                for k in range(8):
+                    for l in range(8):
+                        z = sum(t[k][i] * (a[i][j] - 128) * t[l][j]
+                                for i in range(8) for j in range(8))
+                        assert abs(z - q[k][l] * int(qt[k, l])) <= qt[k, l] / 2 + 1e-9
+                for i in range(8):
+                    for j in range(8):
+                        rec = 128.0 + sum(t[k][i] * (q[k][l] * int(qt[k, l])) * t[l][j]
+                                          for k in range(8) for l in range(8))
+                        assert abs(res["recon"][8 * by + i, 8 * bx + j] - rec) < 1e-9
+                        sse += (a[i][j] - rec) ** 2
+        assert abs(res["sse"] - sse) < 1e-9 * max(1.0, sse)
