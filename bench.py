@@ -309,16 +309,19 @@ class RetentionSweep:
         self.pipe.submit(slot)
 
     def finish(self, slot):
-        """Wait for the step in `slot` and turn its sums into PSNR."""
-        import numpy as np
-        # PSNR = 10 log10(255^2 / MSE), MSE = sum / 576^2 / pixels.
+        """Wait for the step in `slot` and turn its sums into per-plane PSNR and
+        the average PSNR over the planes for every r (Section 3's curve)."""
         sse = self.pipe.take(slot)
-        if getattr(self, "psnr", None) is None or self.psnr.shape != sse.shape:
-            self.psnr = np.empty(sse.shape, dtype=np.float64)
-        with np.errstate(divide="ignore"):
-            np.divide(255.0 ** 2 * 576.0 ** 2 * float(self.size * self.size), sse, out=self.psnr)
-        np.log10(self.psnr, out=self.psnr)
-        self.psnr *= 10.0
+        self.psnr, self.avg_psnr = self.R.rdct_psnr_planes(
+            sse, 45, self.R.SEL_ZIGZAG, [self.size] * self.n, [self.size] * self.n, mean=True)
+
+    def report(self):
+        """Average PSNR over the planes at r = 1..45 (the paper's Fig. 3 measure,
+        on the synthetic planes)."""
+        if getattr(self, "avg_psnr", None) is None:
+            return None
+        return {"psnr_curve": {"avg_psnr_db_r1_45": [round(float(v), 4) for v in self.avg_psnr],
+                               "planes": self.n, "parity_with_paper": "unpinned"}}
 
     def step(self):
         self.submit(0)
@@ -515,7 +518,7 @@ class QualitySweep:
         out = {}
         for nm, a in self.summary["ape"].items():
             out[nm] = {k: {str(r): round(a[k][r - 1], 4) for r in pick} for k in ("mse", "uqi")}
-        return {"ape_percent": out}
+        return {"quality": {"ape_percent": out}}
 
     def cpu_baseline(self, budget_s):
         import oracle as O
@@ -590,18 +593,13 @@ class RaggedBatch:
         self.pipe.submit(slot)
 
     def finish(self, slot):
-        """Wait for the step in `slot` and turn its sums into PSNR."""
+        """Wait for the step in `slot` and turn its sums into per-plane PSNR."""
         import numpy as np
-        # PSNR = 10 log10(255^2 / MSE), MSE = sum * 2^-20 / pixels.
         sse = self.pipe.take(slot)
-        if getattr(self, "psnr_num", None) is None:
-            npx = np.array([it.height * it.width for it in self.items], dtype=np.float64)
-            self.psnr_num = 255.0 ** 2 * 2.0 ** 20 * npx
-            self.psnr = np.empty(len(self.items), dtype=np.float64)
-        with np.errstate(divide="ignore"):
-            np.divide(self.psnr_num, sse, out=self.psnr)
-        np.log10(self.psnr, out=self.psnr)
-        self.psnr *= 10.0
+        if getattr(self, "widths", None) is None:
+            self.widths = np.array([it.width for it in self.items], dtype=np.int32)
+            self.heights = np.array([it.height for it in self.items], dtype=np.int32)
+        self.psnr = self.R.rdct_psnr_planes(sse, 1, self.R.SEL_QUANT, self.widths, self.heights)
 
     def step(self):
         self.submit(0)
@@ -661,6 +659,170 @@ class RaggedBatch:
                           "exact quantisation + float64 inverse + SSE"}
 
 
+class SingleImage:
+    """One 512 x 512 plane (seed 0), r = 10: forward to int32 coefficients,
+    retention, inverse to float32 pixels and the exact error sum in one launch,
+    then the sum read back and its PSNR (the small configuration of Section 3's
+    procedure).  Steps run back to back; `latency()` times single synchronous
+    calls (launch to PSNR on the host)."""
+    name = "single-512x512-r10"
+    workload_key = "single"
+    dtype = "int32+int64"
+
+    def __init__(self, size=512, r=10):
+        import torch
+        from paper_1402_6034_amd import rdct as R, synth
+        self.R = R
+        self.size, self.r = size, r
+        self.img = synth.render(0, size, size, device="cuda")
+        self.nb = (size // 8) ** 2
+        self.sel = R.select(R.SEL_ZIGZAG, r=r)
+        self.coef = torch.empty((self.nb, 64), dtype=torch.int32, device="cuda")
+        self.rec = torch.empty((size, size), dtype=torch.float32, device="cuda")
+        self.sse = torch.empty(1, dtype=torch.int64, device="cuda")
+        self.host = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.psnr = None
+
+    def launch(self, i=0):
+        self.R.compress_eval(self.img, self.sel, 1, self.R.COEF_I32, True, sse=self.sse,
+                             coef=self.coef, recon_out=self.rec)
+
+    kernel_launch = launch
+
+    def step(self):
+        self.launch()
+        self.host.copy_(self.sse, non_blocking=True)
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self.psnr = self.R.rdct_psnr(int(self.host[0]), self.R.SEL_ZIGZAG, self.size, self.size)
+
+    blocks_per_step = property(lambda self: self.nb)
+    # 64 B of pixels in, 256 B of int32 coefficients and 256 B of float pixels out.
+    bytes_per_block = 64 + 256 + 256
+
+    def latency(self, reps=200):
+        """Median and p99 microseconds of one synchronous call (launch, read-back, PSNR)."""
+        import numpy as np
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            self.step()
+            ts.append((time.perf_counter() - t0) * 1e6)
+        return {"p50_us": round(float(np.percentile(ts, 50)), 2),
+                "p99_us": round(float(np.percentile(ts, 99)), 2), "psnr_db": round(self.psnr, 4)}
+
+    def config(self):
+        return {"workload": self.name, "plane": [self.size, self.size], "blocks": self.nb,
+                "r": self.r, "coef": "int32", "recon": "float32"}
+
+    def report(self):
+        return {"latency": self.latency()}
+
+    def cpu_baseline(self, budget_s):
+        import oracle as O
+        img = self.img.cpu().numpy()
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget_s:
+            O.retention_eval(img, [self.r], recon_r=self.r)
+            n += 1
+        dt = time.perf_counter() - t0
+        return {"value": n * self.nb / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
+                "kind": "oracle",
+                "sample": f"{n} passes over the 512 x 512 plane (forward, r = 10, inverse, SSE)"}
+
+
+# rdct_stream patterns: name, and the library kernel whose read:write mix it matches.
+STREAM_PATTERNS = {0: ("read", None), 1: ("write", None), 2: ("copy", None),
+                   3: ("r1w2", "frame quantiser, 64 B in / 128 B out per block"),
+                   4: ("r1w6", "ragged batch, 64 B in / 384 B out per block")}
+
+
+class StreamCalibration:
+    """Practical HBM ceilings: the library's streaming calibration kernel in each
+    read:write mix (pure read, pure write, 1:1, 1:2 as the frame quantiser, 1:6
+    as the ragged batch), nontemporal or regular loads and stores, one unit per
+    wave (as the frame kernel's chunks) or persistent workgroups (as the batch
+    kernel).  The 1:2 mix runs at the frame's size (64 MiB read, 128 MiB written
+    per launch, six buffer sets rotating past the 256 MB last-level cache); the
+    others move 1 GiB or more per launch.  `value` is the best 1:2 rate."""
+    name = "stream-calibration"
+    workload_key = "stream"
+    dtype = "u8"
+
+    def __init__(self):
+        import torch
+        from paper_1402_6034_amd import rdct as R
+        self.R = R
+        self.units = {0: 131072, 1: 65536, 2: 65536, 3: 8192, 4: 208144}
+        self.sets = {0: 1, 1: 1, 2: 1, 3: 6, 4: 1}
+        self.bufs = {}
+        for p, u in self.units.items():
+            rb, wb = R.rdct_stream_unit_bytes(p)
+            self.bufs[p] = [(torch.ones(max(u * rb, 16), dtype=torch.uint8, device="cuda"),
+                             torch.empty(max(u * wb, 1024), dtype=torch.uint8, device="cuda"))
+                            for _ in range(self.sets[p])]
+        self.results = []
+        self.best = {}
+
+    def run_case(self, p, flags, wpc, reps=20):
+        import torch
+        bufs, u = self.bufs[p], self.units[p]
+        rb, wb = self.R.rdct_stream_unit_bytes(p)
+
+        def one(i):
+            src, dst = bufs[i % len(bufs)]
+            self.R.rdct_stream(src if rb else None, dst, u, p, flags, wpc)
+        rounds = sorted(event_time_ms(one, reps) for _ in range(3))
+        ms = rounds[1]
+        gbs = u * (rb + wb) / (ms * 1e-3) / 1e9
+        return ms, gbs
+
+    def sweep(self):
+        for p in self.units:
+            for flags in range(4):
+                for wpc in (0, 2, 4, 8):
+                    ms, gbs = self.run_case(p, flags, wpc)
+                    row = {"pattern": STREAM_PATTERNS[p][0], "nt_loads": bool(flags & 1),
+                           "nt_stores": bool(flags & 2),
+                           "grid": "one unit per wave" if wpc == 0 else f"{wpc} WGs/CU persistent",
+                           "ms": round(ms, 5), "GB/s": round(gbs, 1)}
+                    self.results.append(row)
+                    b = self.best.get(p)
+                    if b is None or gbs > b["GB/s"]:
+                        self.best[p] = row
+                    log(f"[bench] stream {row}")
+
+    def launch(self, i=0):
+        """The 1:2 mix at the frame's size, nontemporal, one unit per wave."""
+        src, dst = self.bufs[3][i % self.sets[3]]
+        self.R.rdct_stream(src, dst, self.units[3], 3, 3, 0)
+
+    kernel_launch = launch
+
+    def step(self):
+        if not self.results:
+            self.sweep()
+        self.launch()
+
+    blocks_per_step = property(lambda self: self.units[3] * 128)
+    bytes_per_block = 64 + 128
+
+    def config(self):
+        return {"workload": self.name,
+                "sizes": {STREAM_PATTERNS[p][0]: {"units": u, "bytes_per_unit":
+                                                  list(self.R.rdct_stream_unit_bytes(p))}
+                          for p, u in self.units.items()}}
+
+    def report(self):
+        return {"stream": {"best": {STREAM_PATTERNS[p][0]: dict(b, matches=STREAM_PATTERNS[p][1])
+                                    for p, b in self.best.items()},
+                           "all": self.results}}
+
+    def cpu_baseline(self, budget_s):
+        return None
+
+
 def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
     """Poisson trace of compression requests (Y + 4:2:0 Cb/Cr planes, resolutions
     256x256 .. 3840x2160, r uniform in 1..45) replayed in real time against the
@@ -715,7 +877,8 @@ def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
 
 
 WORKLOADS = {"frame": FrameQuant, "sweep": RetentionSweep, "ragged": RaggedBatch,
-             "quality": QualitySweep, "codec": CodecFrame}
+             "quality": QualitySweep, "codec": CodecFrame, "single": SingleImage,
+             "stream": StreamCalibration}
 
 
 def _pool_worker(job):
@@ -772,6 +935,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ragged", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="ragged: skip the frame and single-plane figures added to the line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="ragged, sweep: use the tuning cache (or defaults) instead of tuning first")
     ap.add_argument("--serve-requests", type=int, default=None,
@@ -875,6 +1040,36 @@ def main():
                                   "unit": "G wave-instructions/s", "frac": round(rate / peak, 4),
                                   "instructions_per_launch": valu}
 
+    extras = {}
+    if args.workload == "ragged" and not args.no_extras:
+        # The other configurations' headline figures beside the default line:
+        # the 8192^2 quantisation frame (its kernel against the HBM peak) and one
+        # 512^2 plane at r = 10 (throughput and single-call latency).
+        fr = FrameQuant()
+        f_ms = event_time_ms(lambda i: fr.kernel_launch(i), 60)
+        f_bytes = fr.blocks_per_step * fr.bytes_per_block
+        extras["frame"] = {"workload": fr.name, "kernel_ms": round(f_ms, 5),
+                           "achieved_GBs": round(f_bytes / (f_ms * 1e-3) / 1e9, 2),
+                           "frac": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "bytes_per_launch": f_bytes,
+                           "mblocks_per_s": round(fr.blocks_per_step / (f_ms * 1e-3) / 1e6, 1)}
+        del fr
+        one = SingleImage()
+        for _ in range(20):
+            one.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(500):
+            one.launch()
+        torch.cuda.synchronize()
+        s_ms = (time.perf_counter() - t1) * 1e3 / 500
+        extras["single"] = {"workload": one.name, "us_per_image": round(s_ms * 1e3, 2),
+                            "mblocks_per_s": round(one.nb / (s_ms * 1e-3) / 1e6, 1),
+                            "synchronous_call": one.latency()}
+        del one
+        log(f"[bench] frame kernel {extras['frame']['kernel_ms']} ms "
+            f"({extras['frame']['frac']} of peak); single 512^2 {extras['single']['us_per_image']} us")
+
     cpu = None
     if args.cpu_budget > 0:
         log("[bench] timing the CPU oracle on a sample")
@@ -903,7 +1098,8 @@ def main():
     if plain is not None:
         out["plain"] = plain
     if hasattr(wl, "report") and wl.report():
-        out["quality"] = wl.report()
+        out.update(wl.report())
+    out.update(extras)
     if serving is not None:
         out["serving"] = serving
     print(json.dumps(out), flush=True)

@@ -146,6 +146,21 @@ double rdct_sse_unit(int32_t mode);
    MSE = sse_out * rdct_sse_unit(mode) / (width * height); +inf when 0. */
 double rdct_psnr(uint64_t sse, int32_t mode, int32_t width, int32_t height);
 
+/*
+ * PSNR of many planes at once (Section 3: PSNR per image, and the average PSNR
+ * over images as the mean of their dB values).  HOST arrays.
+ *   sse       n * r_count raw sums in units of rdct_sse_unit(mode): plane i's
+ *             r_count sums at sse[i * r_count ...] (a sweep; r_count = 1 otherwise).
+ *   widths, heights   n plane sizes.
+ *   psnr_out  n * r_count values in the layout of sse (+inf for an exact
+ *             reconstruction).
+ *   mean_out  optional (NULL = not written): r_count means over the n planes.
+ * Errors: INVALID_ARG (null arrays, n < 0, r_count < 1, a size <= 0, bad mode).
+ */
+rdct_status_t rdct_psnr_planes(const uint64_t* sse, int32_t n, int32_t r_count, int32_t mode,
+                               const int32_t* widths, const int32_t* heights, double* psnr_out,
+                               double* mean_out);
+
 /* Number of 8x8 blocks of a plane: ceil(h/8) * ceil(w/8). */
 int64_t rdct_num_blocks(int32_t width, int32_t height);
 
@@ -292,6 +307,12 @@ rdct_status_t rdct_codec_pack(const uint16_t* counts, const uint32_t* group_pair
                               uint32_t* offsets, int32_t* packed, int64_t capacity,
                               uint32_t* workspace, void* stream);
 
+/* Decode n pair words of the packed stream (HOST arrays): run_out[i] = word >> 16,
+   value_out[i] = the signed 16-bit low half.  Errors: INVALID_ARG (null arrays
+   with n > 0, n < 0). */
+rdct_status_t rdct_codec_unpack_pairs(const int32_t* words, int64_t n, int32_t* run_out,
+                                      int32_t* value_out);
+
 /* ------------------------------------------------------------------------- */
 /* Comparison transforms and image-quality metrics (Sections 2-4)             */
 /* ------------------------------------------------------------------------- */
@@ -345,6 +366,18 @@ double rdct_quality_sse_unit(int32_t transform);
 
 /* Number of 8x8 windows at stride 1: (width - 7) * (height - 7), 0 if smaller. */
 int64_t rdct_quality_windows(int32_t width, int32_t height);
+
+/*
+ * Metrics of one plane from rdct_quality_sweep's raw sums (Section 3: MSE and
+ * the mean UQI over the plane's windows).  HOST arrays of n entries:
+ *   mse_out[i] = sse[i] * rdct_quality_sse_unit(transform) / (width * height)
+ *   uqi_out[i] = uqi[i] * 2^-32 / rdct_quality_windows(width, height)
+ * Errors: INVALID_ARG (null arrays with n > 0, n < 0, an invalid transform, a
+ * plane smaller than one 8x8 window).
+ */
+rdct_status_t rdct_quality_metrics(const uint64_t* sse, const int64_t* uqi, int32_t n,
+                                   int32_t transform, int32_t width, int32_t height,
+                                   double* mse_out, double* uqi_out);
 
 /* One plane of a quality plan (DEVICE pointer, valid while the plan exists). */
 typedef struct {
@@ -451,6 +484,38 @@ rdct_status_t rdct_server_stats(rdct_server_t* srv, rdct_server_stats_t* out);
 /* Stop the scheduler, wait for launched work, free everything.  Pending requests
    are dropped. */
 void rdct_server_destroy(rdct_server_t* srv);
+
+/* ------------------------------------------------------------------------- */
+/* Bandwidth calibration (no part of the method)                              */
+/* ------------------------------------------------------------------------- */
+
+/* Read:write patterns of rdct_stream, per unit of one wave. */
+typedef enum {
+  RDCT_STREAM_READ = 0,      /* 8 KiB read                                   */
+  RDCT_STREAM_WRITE = 1,     /* 16 KiB written                               */
+  RDCT_STREAM_COPY = 2,      /* 8 KiB read, 8 KiB written                    */
+  RDCT_STREAM_R1W2 = 3,      /* 8 KiB read, 16 KiB written (frame quantiser) */
+  RDCT_STREAM_R1W6 = 4       /* 4 KiB read, 24 KiB written (batch with
+                                int16 coefficients and float reconstruction) */
+} rdct_stream_pattern_t;
+
+/* Bytes one unit of `pattern` reads and writes (either pointer may be NULL). */
+rdct_status_t rdct_stream_unit_bytes(int32_t pattern, int64_t* read_bytes, int64_t* write_bytes);
+
+/*
+ * Move `units` units of `pattern` from src to dst (DEVICE pointers, 16-byte
+ * aligned): the streaming reference the HBM rooflines of the transform kernels
+ * are read against.  Each wave instruction reads or writes 1 KiB (16 bytes per
+ * lane).  src holds units * read bytes; dst holds units * written bytes (at
+ * least 1 KiB for RDCT_STREAM_READ, where it is written only for one value of
+ * the data).  flags: bit 0 = nontemporal loads, bit 1 = nontemporal stores.
+ * wgs_per_cu: 0 = one unit per wave (the grid covers the units), else that many
+ * persistent 4-wave workgroups per compute unit (1..32) stride over them.
+ * Asynchronous on `stream`; no allocation.
+ * Errors: INVALID_ARG, UNSUPPORTED (more than 2^34 units), HIP.
+ */
+rdct_status_t rdct_stream(const void* src, void* dst, int64_t units, int32_t pattern,
+                          int32_t flags, int32_t wgs_per_cu, void* stream);
 
 const char* rdct_status_string(rdct_status_t status);
 

@@ -3,8 +3,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <atomic>
-
 #include "../../include/rdct.h"
 #include "rdct_internal.h"
 #include "rdct_tables.h"
@@ -40,14 +38,6 @@ uint64_t keep_bits(int r) {
   return m;
 }
 
-static int initial_waves_per_wg() {
-  // RDCT_WAVES_PER_WG overrides the default workgroup shape (1, 2 or 4 waves).
-  const char* e = getenv("RDCT_WAVES_PER_WG");
-  const int v = e ? atoi(e) : 1;
-  return (v == 1 || v == 2 || v == 4) ? v : 1;
-}
-static std::atomic<int> g_waves_per_wg{initial_waves_per_wg()};  // measured best: 1
-
 int device_cu_count() {
   int dev = 0, n = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -55,8 +45,6 @@ int device_cu_count() {
     return 256;
   return n;
 }
-
-int default_waves_per_wg() { return g_waves_per_wg.load(); }
 
 rdct_status_t check_sel(const rdct_select_t* s, SelInfo* out) {
   if (!s) return RDCT_ERR_INVALID_ARG;
@@ -108,11 +96,8 @@ bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 
 
 rdct_status_t check_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch,
-                                 int64_t max_blocks) {
-  if (!src || w <= 0 || h <= 0 || pitch < w) return RDCT_ERR_INVALID_ARG;
-  const int64_t nb = (int64_t)((w + 7) / 8) * ((h + 7) / 8);
-  if (nb > max_blocks) return RDCT_ERR_UNSUPPORTED;
-  return RDCT_OK;
+                          int64_t max_blocks) {
+  return check_plane_dims(src, w, h, pitch, max_blocks);
 }
 
 Plane make_plane(const uint8_t* src, int32_t w, int32_t h, int64_t pitch) {
@@ -154,13 +139,13 @@ rdct_status_t rdct_forward(const uint8_t* src, int32_t width, int32_t height, in
   P.r_count = 1;
   P.shift = si.shift;
   return hip_status(launch_plane(si.sel, co, false, EV_NONE, P, si.qc,
-                                 default_waves_per_wg(), (hipStream_t)stream));
+                                 kPlaneWavesPerWg, (hipStream_t)stream));
 }
 
 rdct_status_t rdct_inverse(const void* coef, rdct_coef_t coef_type, int32_t width, int32_t height,
                            const rdct_select_t* sel, float* dst, int64_t dst_pitch, void* stream) {
   if (!coef || !dst || width <= 0 || height <= 0 || dst_pitch < width) return RDCT_ERR_INVALID_ARG;
-  if ((int64_t)((width + 7) / 8) * ((height + 7) / 8) > kMaxBlocks) return RDCT_ERR_UNSUPPORTED;
+  if (blocks_of(width, height) > kMaxBlocks) return RDCT_ERR_UNSUPPORTED;
   if (!aligned(coef, 16) || !aligned(dst, 4)) return RDCT_ERR_INVALID_ARG;
   SelInfo si;
   rdct_status_t st = check_sel(sel, &si);
@@ -220,22 +205,7 @@ rdct_status_t rdct_compress_eval(const uint8_t* src, int32_t width, int32_t heig
   hipError_t e = launch_zero_u64(sse_out, r_count, (hipStream_t)stream);
   if (e != hipSuccess) return RDCT_ERR_HIP;
   return hip_status(launch_plane(si.sel, co, recon_out != nullptr, ev, P, si.qc,
-                                 default_waves_per_wg(), (hipStream_t)stream));
-}
-
-double rdct_sse_unit(int32_t mode) {
-  return mode == RDCT_SEL_QUANT ? 1.0 / 1048576.0 : 1.0 / 331776.0;
-}
-
-double rdct_psnr(uint64_t sse, int32_t mode, int32_t width, int32_t height) {
-  if (sse == 0) return INFINITY;
-  const double mse = (double)sse * rdct_sse_unit(mode) / ((double)width * (double)height);
-  return 10.0 * log10(255.0 * 255.0 / mse);
-}
-
-int64_t rdct_num_blocks(int32_t width, int32_t height) {
-  if (width <= 0 || height <= 0) return 0;
-  return (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+                                 kPlaneWavesPerWg, (hipStream_t)stream));
 }
 
 const char* rdct_status_string(rdct_status_t s) {

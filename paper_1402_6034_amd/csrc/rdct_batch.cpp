@@ -33,17 +33,31 @@
 
 using namespace rdct;
 
+// A plan runs one or two groups of planes: quantisation plans score
+// whole-block planes in the coefficient domain and planes with partial blocks
+// pixel by pixel (the error kind rdct_compress_eval takes for each), so each
+// plane's sum has the same bits alone and in any batch.  The device arrays
+// hold group 0's planes, then group 1's; a work item's plane index counts from
+// its group's first plane.
+struct PlanGroup {
+  int ev = EV_SPATIAL;
+  int32_t plane0 = 0, n_planes = 0;  // descriptors plane0 .. plane0 + n_planes - 1
+  int32_t item0 = 0, n_items = 0;    // work items item0 .. item0 + n_items - 1
+};
+
 struct rdct_batch_plan {
-  int sel = SEL_ZZ, co = CO_NONE, ev = EV_SPATIAL;
+  int sel = SEL_ZZ, co = CO_NONE;
   bool recon = false;
   int32_t n_planes = 0, n_items = 0;
   int32_t r_count = 1;   // error sums per plane (a retention sweep when > 1)
   int64_t n_blocks = 0;
+  int n_groups = 1;
+  PlanGroup group[2];
   uint64_t* sse = nullptr;
   Plane* d_planes = nullptr;
   QuantConsts* d_tables = nullptr;
   WorkItem* d_items = nullptr;
-  int32_t* d_first = nullptr;  // plane b's items: d_first[b] .. d_first[b + 1] - 1
+  int32_t* d_first = nullptr;  // descriptor b's items: d_first[b] .. d_first[b + 1] - 1
   rdct_tuning_t tuning{};
   int device = 0;
   int n_cu = 256;
@@ -71,22 +85,33 @@ void free_plan(rdct_batch_plan* p) {
   delete p;
 }
 
-int grid_of(const rdct_batch_plan* p, const rdct_tuning_t& t) {
+int grid_of(const rdct_batch_plan* p, const PlanGroup& g, const rdct_tuning_t& t) {
   const int wpg = t.waves_per_wg;
-  const int max_grid = (p->n_items + wpg - 1) / wpg;
+  const int max_grid = (g.n_items + wpg - 1) / wpg;
   return std::max(1, std::min(p->n_cu * t.wgs_per_cu, max_grid));
 }
 
 hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t s) {
-  if (t.layout == RDCT_LAYOUT_PER_PLANE) {
-    if (p->n_items == 0) return launch_zero_u64(p->sse, (int64_t)p->n_planes * p->r_count, s);
-    return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables, p->d_items,
-                        p->n_items, p->n_planes, t.waves_per_wg, s, p->d_first);
+  hipError_t e = hipSuccess;
+  if (t.layout != RDCT_LAYOUT_PER_PLANE) {
+    e = launch_zero_u64(p->sse, (int64_t)p->n_planes * p->r_count, s);
+    if (e != hipSuccess) return e;
   }
-  hipError_t e = launch_zero_u64(p->sse, (int64_t)p->n_planes * p->r_count, s);
-  if (e != hipSuccess) return e;
-  return launch_batch(p->sel, p->co, p->recon, p->ev, p->d_planes, p->d_tables,
-                      p->d_items, p->n_items, grid_of(p, t), t.waves_per_wg, s);
+  for (int gi = 0; gi < p->n_groups; ++gi) {
+    const PlanGroup& g = p->group[gi];
+    if (t.layout == RDCT_LAYOUT_PER_PLANE) {
+      // Each workgroup stores its plane's sums; items are indexed from the
+      // whole list through the group's first-item entries.
+      e = launch_batch(p->sel, p->co, p->recon, g.ev, p->d_planes + g.plane0, p->d_tables,
+                       p->d_items, g.n_items, g.n_planes, t.waves_per_wg, s,
+                       p->d_first + g.plane0);
+    } else {
+      e = launch_batch(p->sel, p->co, p->recon, g.ev, p->d_planes + g.plane0, p->d_tables,
+                       p->d_items + g.item0, g.n_items, grid_of(p, g, t), t.waves_per_wg, s);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 rdct_status_t capture(rdct_batch_plan* p) {
@@ -110,20 +135,15 @@ rdct_status_t capture(rdct_batch_plan* p) {
   return RDCT_OK;
 }
 
-bool valid_tuning(const rdct_tuning_t& t) {
-  return (t.waves_per_wg == 1 || t.waves_per_wg == 2 || t.waves_per_wg == 4) &&
-         t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16 &&
-         (t.layout == RDCT_LAYOUT_STRIDED || t.layout == RDCT_LAYOUT_PER_PLANE);
-}
-
 std::string plan_key(const rdct_batch_plan* p) {
   // Size classes: log2 of the block count and of the plane count.
   int cls = 0, pcls = 0;
   for (int64_t b = p->n_blocks; b > 1; b >>= 1) ++cls;
   for (int64_t b = p->n_planes; b > 1; b >>= 1) ++pcls;
   char buf[128];
+  const int ev = p->n_groups == 2 ? 10 * p->group[0].ev + p->group[1].ev : p->group[0].ev;
   snprintf(buf, sizeof(buf), "gfx950/batch/sel%d/co%d/recon%d/ev%d/log2blocks%d/log2planes%d",
-           p->sel, p->co, p->recon ? 1 : 0, p->ev, cls, pcls);
+           p->sel, p->co, p->recon ? 1 : 0, ev, cls, pcls);
   return buf;
 }
 
@@ -150,10 +170,8 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   std::vector<QuantConsts> tables;
   std::map<std::vector<uint16_t>, int> table_index;
   int sel_kind = -1;
-  bool all_full = true;
+  std::vector<bool> coef_err(n, false);
   int64_t n_blocks = 0;
-  std::vector<WorkItem> items;
-  std::vector<int32_t> first(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const rdct_plane_desc_t& d = planes[i];
     rdct_status_t st = check_plane(d.src, d.width, d.height, d.src_pitch, kMaxEvalBlocks);
@@ -194,24 +212,59 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
       }
       P.table = it->second;
     }
-    if ((d.width % 8) != 0 || (d.height % 8) != 0) all_full = false;
+    coef_err[i] = si.sel == SEL_Q && r_count == 1 && whole_blocks(d.width, d.height);
     hp[i] = P;
-    first[i] = (int32_t)std::min<size_t>(items.size(), 0x7fffffff);
-    for (int t0 = 0; t0 < P.nblocks; t0 += 128) items.push_back(WorkItem{i, t0});
     n_blocks += P.nblocks;
   }
-  if (items.size() > (size_t)0x7fffffff) return RDCT_ERR_UNSUPPORTED;
-  first[n] = (int32_t)items.size();
   if (tables.empty()) {
     tables.emplace_back();
     memset(&tables[0], 0, sizeof(QuantConsts));
+  }
+
+  // Groups (see PlanGroup) and the device order of the descriptors.
+  std::vector<int> order;
+  const int n_coef = flagged_first(coef_err, &order);
+  PlanGroup groups[2];
+  int n_groups = 0;
+  if (n_coef > 0) {
+    groups[n_groups].ev = EV_COEF;
+    groups[n_groups].plane0 = 0;
+    groups[n_groups].n_planes = n_coef;
+    ++n_groups;
+  }
+  if (n_coef < n) {
+    groups[n_groups].ev = r_count > 1 ? EV_SWEEP : EV_SPATIAL;
+    groups[n_groups].plane0 = n_coef;
+    groups[n_groups].n_planes = n - n_coef;
+    ++n_groups;
+  }
+  std::vector<Plane> dev_planes(n);
+  std::vector<WorkItem> items;
+  std::vector<int32_t> first(n + 1, 0);
+  for (int gi = 0; gi < n_groups; ++gi) {
+    PlanGroup& g = groups[gi];
+    std::vector<int64_t> nb(g.n_planes);
+    for (int j = 0; j < g.n_planes; ++j) {
+      dev_planes[g.plane0 + j] = hp[order[g.plane0 + j]];
+      nb[j] = dev_planes[g.plane0 + j].nblocks;
+    }
+    std::vector<WorkItem> gitems;
+    std::vector<int32_t> gfirst;
+    if (!build_work_list(nb.data(), g.n_planes, &gitems, &gfirst) ||
+        items.size() + gitems.size() > (size_t)INT32_MAX)
+      return RDCT_ERR_UNSUPPORTED;
+    g.item0 = (int32_t)items.size();
+    g.n_items = (int32_t)gitems.size();
+    for (int j = 0; j <= g.n_planes; ++j) first[g.plane0 + j] = g.item0 + gfirst[j];
+    items.insert(items.end(), gitems.begin(), gitems.end());
   }
 
   rdct_batch_plan* p = new rdct_batch_plan();
   p->sel = sel_kind;
   p->co = co;
   p->recon = want_recon;
-  p->ev = r_count > 1 ? EV_SWEEP : (sel_kind == SEL_Q && all_full) ? EV_COEF : EV_SPATIAL;
+  p->n_groups = n_groups;
+  for (int gi = 0; gi < n_groups; ++gi) p->group[gi] = groups[gi];
   p->r_count = r_count;
   p->n_planes = n;
   p->n_items = (int32_t)items.size();
@@ -262,7 +315,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     free_plan(p);
     return RDCT_ERR_NO_MEMORY;
   }
-  ok = hipMemcpy(p->d_planes, hp.data(), sizeof(Plane) * n, hipMemcpyHostToDevice) == hipSuccess &&
+  ok = hipMemcpy(p->d_planes, dev_planes.data(), sizeof(Plane) * n, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, tables.data(), sizeof(QuantConsts) * tables.size(),
                  hipMemcpyHostToDevice) == hipSuccess &&
        (items.empty() || hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(),

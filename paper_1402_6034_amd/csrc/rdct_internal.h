@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/rdct.h"
+#include "rdct_host.h"
 
 namespace rdct {
 
@@ -98,13 +99,6 @@ enum CoefKind { CO_NONE = 0, CO_I32 = 1, CO_I16 = 2, CO_F32 = 3 };
 enum EvalKind { EV_NONE = 0, EV_SPATIAL = 1, EV_SWEEP = 2, EV_COEF = 3 };
 enum InvKind { INV_INT_I32 = 0, INV_INT_I16 = 1, INV_F32 = 2, INV_Q_I32 = 3, INV_Q_I16 = 4 };
 
-// Work item of the persistent batch kernel: `count` (<= 128) consecutive blocks
-// of plane `plane` starting at block `t0`.
-struct WorkItem {
-  int32_t plane;
-  int32_t t0;
-};
-
 // Launch geometry choices (tuned per shape class).
 struct Geometry {
   int32_t waves_per_wg;   // 1, 2, 4, 8
@@ -133,8 +127,10 @@ hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes
                         int32_t waves_per_wg, hipStream_t stream,
                         const int32_t* first = nullptr);
 
+// Compute units of the current device (looked up on every call).
 int device_cu_count();
-int default_waves_per_wg();
+// Waves per workgroup of the single-plane kernels (measured best: one).
+constexpr int kPlaneWavesPerWg = 1;
 
 constexpr int64_t kMaxBlocks = 1ll << 26;   // transform calls
 constexpr int64_t kMaxEvalBlocks = 6000000;  // evaluation: the uint64 SSE sums cannot wrap

@@ -156,45 +156,6 @@ __device__ __forceinline__ void flush_stage(const uint8_t* stage, void* coef, in
 }
 
 // ---------------------------------------------------------------------------
-// Inverse of one block of the pair + reconstruction + squared error.
-// Retention: R = C0^T (D' (M . Y) D') C0 in int32 (|R| <= 576 * 2040), A' = R/576.
-// Returns the block's exact sum of (576 (A - shift) - R)^2 over its own pixels.
-// ---------------------------------------------------------------------------
-template <bool RECON, bool SSE>
-__device__ __forceinline__ uint64_t retention_inverse(const Plane& P, const s16x2 (&v)[8][8],
-                                                      uint64_t keep, const uint32_t (&a)[16],
-                                                      int x0, int y0, int h) {
-  int w[8][8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-#pragma unroll
-    for (int l = 0; l < 8; ++l)
-      w[k][l] = ((keep >> (k * 8 + l)) & 1) ? half(v[k][l], h) * (kDp[k] * kDp[l]) : 0;
-  pass2d<int, false>(w);
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if constexpr (RECON) {
-      float px[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        px[j] = (float)__builtin_fma((double)w[i][j], 1.0 / 576.0, (double)P.shift);
-      store_row(P, x0, y0 + i, px);
-    }
-    if constexpr (SSE) {
-      const bool row_ok = y0 + i < P.height;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int e = 576 * (pixel(a, i, j) - P.shift) - w[i][j];
-        const double ed = (row_ok && x0 + j < P.width) ? (double)e : 0.0;
-        acc = __builtin_fma(ed, ed, acc);
-      }
-    }
-  }
-  return (uint64_t)acc;  // exact: < 2^53 per block
-}
-
-// ---------------------------------------------------------------------------
 // Quantisation path.  Both blocks of a lane's pair are quantised together, so
 // every table constant is read once per chunk; q of the high block waits in
 // registers (16-bit pairs) while the low block's stage is written out.
@@ -321,12 +282,20 @@ constexpr int kReconSlot = 64 * 32 + 16;
 constexpr int kReconStageBytes = 4 * kReconSlot;
 
 // LDS bytes of a wave's stage: the coefficient stage, or the reconstruction
-// staging of whole-block quantisation planes if that is larger.
+// staging (whole-block quantisation planes; keep-r planes whose blocks are
+// whole) if that is larger.
 template <int SEL, int CO, bool RECON, int EV>
 constexpr int wave_stage_bytes() {
   constexpr int coef = Stage<CO>::wave_bytes;
-  return (SEL == SEL_Q && RECON && EV == EV_COEF && kReconStageBytes > coef) ? kReconStageBytes
-                                                                              : coef;
+  constexpr bool staged = RECON && ((SEL == SEL_Q && EV == EV_COEF) || SEL == SEL_ZZ);
+  return (staged && kReconStageBytes > coef) ? kReconStageBytes : coef;
+}
+
+// Reconstruction rows go through the stage when the plane is made of whole
+// blocks (every staged piece lies inside the plane); planes with partial
+// blocks store row pieces clipped to the plane.
+__device__ __forceinline__ bool recon_stageable(const Plane& P) {
+  return ((P.width | P.height) & 7) == 0;
 }
 
 __device__ __forceinline__ void recon_stage_row(uint8_t* stage_wave, int slot, int lane,
@@ -383,6 +352,63 @@ __device__ __forceinline__ void recon_flush_rows(const Plane& P, const uint8_t* 
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of one block of the pair + reconstruction + squared error.
+// Retention: R = C0^T (D' (M . Y) D') C0 in int32 (|R| <= 576 * 2040), A' = R/576.
+// Returns the block's exact sum of (576 (A - shift) - R)^2 over its own pixels.
+// With STAGE (wave-uniform; whole-block planes) every lane of the wave takes
+// part -- lanes without a block compute on zeros and are masked at the store
+// and by the caller -- and rows leave through the stage four at a time.
+// ---------------------------------------------------------------------------
+template <bool RECON, bool SSE>
+__device__ __forceinline__ uint64_t retention_inverse(const Plane& P, const s16x2 (&v)[8][8],
+                                                      uint64_t keep, const uint32_t (&a)[16],
+                                                      int x0, int y0, int h, bool stage,
+                                                      uint8_t* stage_wave, int lane, int nvalid) {
+  int w[8][8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      w[k][l] = ((keep >> (k * 8 + l)) & 1) ? half(v[k][l], h) * (kDp[k] * kDp[l]) : 0;
+  pass2d<int, false>(w);
+  ReconFlush fl;
+  if constexpr (RECON) {
+    if (stage) fl = recon_flush_setup(P, x0, y0, nvalid, lane);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if constexpr (RECON) {
+      float px[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        px[j] = (float)__builtin_fma((double)w[i][j], 1.0 / 576.0, (double)P.shift);
+      if (stage) {
+        recon_stage_row(stage_wave, i & 3, lane, px);
+        if ((i & 3) == 3) {
+          const int rows[4] = {i - 3, i - 2, i - 1, i};
+          wave_sync();
+          recon_flush_rows(P, stage_wave, fl, rows, lane);
+          wave_sync();
+        }
+      } else {
+        store_row(P, x0, y0 + i, px);
+      }
+    }
+    if constexpr (SSE) {
+      const bool row_ok = y0 + i < P.height;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = 576 * (pixel(a, i, j) - P.shift) - w[i][j];
+        const double ed = (row_ok && x0 + j < P.width) ? (double)e : 0.0;
+        acc = __builtin_fma(ed, ed, acc);
+      }
+    }
+  }
+  return (uint64_t)acc;  // exact: < 2^53 per block
 }
 
 // Row pass (over l) in float64 for block h of the pair.  Rows i and 7 - i of
@@ -583,14 +609,21 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
   constexpr bool SP = (EV == EV_SPATIAL);
   if constexpr (RECON || SP) {
     uint64_t s = 0;
+    const bool stage = RECON && recon_stageable(P);
     // One block at a time keeps a single 8x8 inverse live in registers.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      if (!(h ? vh : vl)) continue;
+      const bool valid = h ? vh : vl;
+      // A staged store is a wave-wide operation: every lane takes part.
+      if (!valid && !stage) continue;
       uint32_t a[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
-      s += retention_inverse<RECON, SP>(P, v, keep, a, h ? xh : xl, h ? yh : yl, h);
+      const int first = t0 + 64 * h;
+      const uint64_t e = retention_inverse<RECON, SP>(P, v, keep, a, h ? xh : xl, h ? yh : yl, h,
+                                                      stage, stage_wave, lane,
+                                                      min(64, max(0, P.nblocks - first)));
+      s += valid ? e : 0;
     }
     if constexpr (SP) return s;
   }
@@ -827,20 +860,47 @@ __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ pl
 }
 
 // ---------------------------------------------------------------------------
-// Inverse from coefficients: one block per lane.
+// Inverse from coefficients: one block per lane, 64 consecutive blocks per
+// wave.  For planes of whole blocks the rows leave through the wave's LDS
+// stage, four at a time, as 1 KB contiguous pieces (see recon_flush_rows);
+// lanes past the plane's end then recompute the wave's first block and are
+// masked at the store.  Planes with partial blocks store clipped row pieces.
 // ---------------------------------------------------------------------------
 template <int KIND>
 __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, Plane P,
                                                  QuantConsts qc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P.nblocks) return;
-  const int by = t / P.nbx, bx = t - by * P.nbx;
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int t0 = blockIdx.x * blockDim.x + wave * 64;
+  if (t0 >= P.nblocks) return;  // the whole wave
+  const int t = t0 + lane;
+  const bool valid = t < P.nblocks;
+  const int tb = valid ? t : t0;
+  const int by = tb / P.nbx, bx = tb - by * P.nbx;
   const int x0 = bx * 8, y0 = by * 8;
+  const bool stage = recon_stageable(P);
+  uint8_t* stage_wave = reinterpret_cast<uint8_t*>(lds) + wave * kReconStageBytes;
+  ReconFlush fl;
+  if (stage) fl = recon_flush_setup(P, x0, y0, min(64, P.nblocks - t0), lane);
+  auto emit = [&](int i, const float (&px)[8]) {
+    if (stage) {
+      recon_stage_row(stage_wave, i & 3, lane, px);
+      if ((i & 3) == 3) {
+        const int rows[4] = {i - 3, i - 2, i - 1, i};
+        wave_sync();
+        recon_flush_rows(P, stage_wave, fl, rows, lane);
+        wave_sync();
+      }
+    } else if (valid) {
+      store_row(P, x0, y0 + i, px);
+    }
+  };
   if constexpr (KIND == INV_INT_I32 || KIND == INV_INT_I16) {
     const uint64_t keep = P.keep;
     int w[8][8];
     if constexpr (KIND == INV_INT_I32) {
-      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)t * 16;
+      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)tb * 16;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int4 u = p[2 * k], s = p[2 * k + 1];
@@ -848,7 +908,7 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
         w[k][4] = s.x; w[k][5] = s.y; w[k][6] = s.z; w[k][7] = s.w;
       }
     } else {
-      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)t * 8;
+      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)tb * 8;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const uint4 u = p[k];
@@ -872,13 +932,13 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         px[j] = (float)__builtin_fma((double)w[i][j], 1.0 / 576.0, (double)P.shift);
-      store_row(P, x0, y0 + i, px);
+      emit(i, px);
     }
   } else {
     double w[8][8];
     if constexpr (KIND == INV_F32) {
       const uint64_t keep = P.keep;
-      const float4* p = reinterpret_cast<const float4*>(coef) + (int64_t)t * 16;
+      const float4* p = reinterpret_cast<const float4*>(coef) + (int64_t)tb * 16;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const float4 u = p[2 * k], s = p[2 * k + 1];
@@ -888,7 +948,7 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
           w[k][l] = ((keep >> (k * 8 + l)) & 1) ? (double)z[l] * scale_kl(k, l) : 0.0;
       }
     } else if constexpr (KIND == INV_Q_I32) {
-      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)t * 16;
+      const int4* p = reinterpret_cast<const int4*>(coef) + (int64_t)tb * 16;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int4 u = p[2 * k], s = p[2 * k + 1];
@@ -897,7 +957,7 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
         for (int l = 0; l < 8; ++l) w[k][l] = (double)q[l] * qc.dq[k * 8 + l];
       }
     } else {
-      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)t * 8;
+      const uint4* p = reinterpret_cast<const uint4*>(coef) + (int64_t)tb * 8;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const uint4 u = p[k];
@@ -916,7 +976,7 @@ __global__ __launch_bounds__(256) void k_inverse(const void* __restrict__ coef, 
       float px[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) px[j] = (float)(w[i][j] + sh);
-      store_row(P, x0, y0 + i, px);
+      emit(i, px);
     }
   }
 }
@@ -934,7 +994,7 @@ constexpr int kPlaneWavesPerCU = 8;
 
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg, hipStream_t s) {
-  static const int n_cu = device_cu_count();
+  const int n_cu = device_cu_count();
   const int chunks = (P.nblocks + 127) / 128;
   int grid = (chunks + wpg - 1) / wpg;
   if constexpr (EV != EV_NONE) {
@@ -1034,12 +1094,13 @@ hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t hei
   P.shift = shift;
   if (P.nblocks <= 0) return hipSuccess;
   const dim3 grid((P.nblocks + 255) / 256), block(256);
+  const size_t lds = 4 * (size_t)kReconStageBytes;  // one stage per wave
   switch (kind) {
-    case INV_INT_I32: hipLaunchKernelGGL(k_inverse<INV_INT_I32>, grid, block, 0, s, coef, P, qc); break;
-    case INV_INT_I16: hipLaunchKernelGGL(k_inverse<INV_INT_I16>, grid, block, 0, s, coef, P, qc); break;
-    case INV_F32: hipLaunchKernelGGL(k_inverse<INV_F32>, grid, block, 0, s, coef, P, qc); break;
-    case INV_Q_I32: hipLaunchKernelGGL(k_inverse<INV_Q_I32>, grid, block, 0, s, coef, P, qc); break;
-    case INV_Q_I16: hipLaunchKernelGGL(k_inverse<INV_Q_I16>, grid, block, 0, s, coef, P, qc); break;
+    case INV_INT_I32: hipLaunchKernelGGL(k_inverse<INV_INT_I32>, grid, block, lds, s, coef, P, qc); break;
+    case INV_INT_I16: hipLaunchKernelGGL(k_inverse<INV_INT_I16>, grid, block, lds, s, coef, P, qc); break;
+    case INV_F32: hipLaunchKernelGGL(k_inverse<INV_F32>, grid, block, lds, s, coef, P, qc); break;
+    case INV_Q_I32: hipLaunchKernelGGL(k_inverse<INV_Q_I32>, grid, block, lds, s, coef, P, qc); break;
+    case INV_Q_I16: hipLaunchKernelGGL(k_inverse<INV_Q_I16>, grid, block, lds, s, coef, P, qc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -53,21 +53,6 @@ struct rdct_quality_plan {
 
 extern "C" {
 
-double rdct_quality_sse_unit(int32_t transform) {
-  switch (transform) {
-    case RDCT_T_RDCT: return 1.0 / (576.0 * 576.0);
-    case RDCT_T_SDCT: return 1.0 / (64.0 * 64.0);
-    case RDCT_T_DCT:
-    case RDCT_T_RDCT_CEIL: return 1.0 / 1048576.0;
-    default: return 0.0;
-  }
-}
-
-int64_t rdct_quality_windows(int32_t width, int32_t height) {
-  if (width < 8 || height < 8) return 0;
-  return (int64_t)(width - 7) * (int64_t)(height - 7);
-}
-
 rdct_status_t rdct_quality_sweep(const uint8_t* src, int32_t width, int32_t height,
                                  int64_t src_pitch, int32_t transform, int32_t r_first,
                                  int32_t r_count, uint64_t* sse_out, int64_t* uqi_out,

@@ -7,11 +7,21 @@
 // their error sums into completions and freeing their memory, and (b) whenever a
 // stream is free, forms the next batch from the oldest pending requests that fit
 // in the device budget, and launches it: plane uploads, the descriptor upload,
-// the zeroing kernel, the persistent batch kernel and the read-back of the error
-// sums, all asynchronous on that stream, followed by an event.  Batches on
-// different streams overlap on the device.  The per-block arithmetic is the
-// same device code as the single-plane calls, so results do not depend on what
-// a request was batched with.
+// the zeroing kernel, the persistent batch kernel(s) and the read-back of the
+// error sums, all asynchronous on that stream, followed by the stream's event.
+// Batches on different streams overlap on the device.  The per-block arithmetic
+// is the same device code as the single-plane calls, and every plane is scored
+// with the error kind the single-plane call takes for it, so results do not
+// depend on what a request was batched with.
+//
+// Device memory: the budget holds 256 bytes for the plain path's error sum,
+// one fixed metadata region per stream (descriptors, tables, work items and
+// sums of the batch in flight on that stream) and the plane arena.  Pinned host
+// memory: the staging arena for submitted planes and one metadata mirror per
+// stream.  A request is refused at submit if it could not run alone (its planes
+// larger than the plane arena or the staging, or its metadata larger than a
+// region), so the oldest pending request can always start once nothing else is
+// in flight.
 #include <math.h>
 #include <string.h>
 
@@ -32,54 +42,6 @@ using namespace rdct;
 
 namespace {
 
-// First-fit allocator over [0, size) with a coalescing free list.
-class Arena {
- public:
-  void reset(int64_t size, int64_t align) {
-    size_ = size;
-    align_ = align;
-    used_ = 0;
-    free_.clear();
-    if (size > 0) free_[0] = size;
-  }
-  int64_t alloc(int64_t bytes) {
-    bytes = round(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const int64_t off = it->first, rest = it->second - bytes;
-        free_.erase(it);
-        if (rest > 0) free_[off + bytes] = rest;
-        used_ += bytes;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off, int64_t bytes) {
-    bytes = round(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  int64_t in_use() const { return used_; }
-  int64_t round(int64_t b) const { return (b + align_ - 1) / align_ * align_; }
-
- private:
-  std::map<int64_t, int64_t> free_;
-  int64_t size_ = 0, align_ = 256, used_ = 0;
-};
-
 struct PlaneSlot {
   int32_t w = 0, h = 0;
   int64_t host_off = -1;  // staging (tightly packed rows)
@@ -98,11 +60,7 @@ struct Request {
 
 struct Batch {
   std::vector<Request> reqs;
-  int stream = 0;
-  hipEvent_t done = nullptr;
-  int64_t dev_off = -1, dev_bytes = 0;    // descriptors, tables, items, sums
-  int64_t host_off = -1, host_bytes = 0;  // pinned mirror of the same + read-back
-  int64_t o_sse = 0;                      // offset of the error sums in both blocks
+  int stream = 0;                         // its metadata region is the stream's
   int n_planes = 0;
   int64_t n_blocks = 0;
   double t_launch = 0;
@@ -116,10 +74,14 @@ struct rdct_server {
   rdct_server_cfg_t cfg{};
   int device = 0;
   int n_cu = 256;
-  uint8_t* dev_base = nullptr;
-  uint8_t* host_base = nullptr;
-  Arena dev, host;
+  uint8_t* dev_base = nullptr;    // budget_bytes of device memory
+  uint8_t* host_base = nullptr;   // staging_bytes of pinned host memory
+  uint8_t* host_meta = nullptr;   // n_streams metadata mirrors, pinned
+  int64_t meta_cap = 0;           // bytes of one stream's metadata region
+  int64_t plane_base = 0;         // offset of the plane arena in dev_base
+  Arena dev, host;                // plane arena (offsets from plane_base), staging
   hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t events[4] = {nullptr, nullptr, nullptr, nullptr};
   bool stream_busy[4] = {false, false, false, false};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -136,20 +98,31 @@ struct rdct_server {
   double now_us() const {
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   }
+  uint8_t* dev_meta(int stream) const { return dev_base + 256 + (int64_t)stream * meta_cap; }
+  uint8_t* host_meta_of(int stream) const { return host_meta + (int64_t)stream * meta_cap; }
+  uint8_t* plane_ptr(const PlaneSlot& p) const { return dev_base + plane_base + p.dev_off; }
 };
 
 namespace {
 
-// Device bytes a batch needs for its descriptors, tables, work items and sums.
-int64_t batch_meta_bytes(int n_planes, int n_tables, int64_t n_items) {
-  return (int64_t)sizeof(Plane) * n_planes + (int64_t)sizeof(QuantConsts) * n_tables +
-         (int64_t)sizeof(WorkItem) * n_items + 8 * (int64_t)n_planes + 4 * 256;
+const MetaSizes kMetaSizes = {(int64_t)sizeof(Plane), (int64_t)sizeof(QuantConsts),
+                              (int64_t)sizeof(WorkItem)};
+
+// Bytes of one stream's metadata region: a sixteenth of the budget, between
+// 64 KiB and 4 MiB (4 MiB holds half a million work items, or 64 M blocks).
+int64_t meta_region_bytes(int64_t budget) {
+  const int64_t m = std::min<int64_t>(4 << 20, std::max<int64_t>(64 << 10, budget / 16));
+  return m / 256 * 256;
 }
 
-int64_t request_items(const Request& r) {
-  int64_t n = 0;
-  for (int i = 0; i < r.n; ++i) n += (rdct_num_blocks(r.p[i].w, r.p[i].h) + 127) / 128;
-  return n;
+AdmitRequest admit_view(const Request& r) {
+  AdmitRequest a;
+  a.kind = r.sel;
+  a.n = r.n;
+  a.items = 0;
+  for (int i = 0; i < 3; ++i) a.bytes[i] = i < r.n ? r.p[i].bytes : 0;
+  for (int i = 0; i < r.n; ++i) a.items += items_of(blocks_of(r.p[i].w, r.p[i].h));
+  return a;
 }
 
 void complete(rdct_server* s, const Request& r, int status, const uint64_t* sse, double t_done,
@@ -178,6 +151,29 @@ void release_request(rdct_server* s, const Request& r) {
   }
 }
 
+// Offsets of the sections of a batch's metadata block (same on host and device).
+struct MetaLayout {
+  int64_t planes, tables, items, sse, end;
+};
+
+MetaLayout meta_layout(int64_t n_planes, int64_t n_tables, int64_t n_items) {
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  MetaLayout m;
+  m.planes = 0;
+  m.tables = up(m.planes + (int64_t)sizeof(Plane) * n_planes);
+  m.items = up(m.tables + (int64_t)sizeof(QuantConsts) * std::max<int64_t>(1, n_tables));
+  m.sse = up(m.items + (int64_t)sizeof(WorkItem) * n_items);
+  m.end = up(m.sse + 8 * n_planes);
+  return m;
+}
+
+// Offset of the error sums in the metadata block of a batch (kept for retiring it).
+int64_t batch_sse_offset(const Batch& b) {
+  int64_t items = 0;
+  for (const Request& r : b.reqs) items += admit_view(r).items;
+  return meta_layout(b.n_planes, (int64_t)b.reqs.size(), items).sse;
+}
+
 // Launch one batch on stream b.stream.  Called with the lock held.
 hipError_t launch(rdct_server* s, Batch& b) {
   hipStream_t st = s->streams[b.stream];
@@ -194,60 +190,79 @@ hipError_t launch(rdct_server* s, Batch& b) {
     }
     table_of.push_back(t);
   }
-  const int n_tables = std::max<int>(1, (int)tables.size());
   int64_t n_items = 0;
-  for (const Request& r : b.reqs) n_items += request_items(r);
-  // Layout of the descriptor block (same offsets on host and device).
-  const int64_t o_planes = 0;
-  const int64_t o_tables = s->dev.round(o_planes + (int64_t)sizeof(Plane) * b.n_planes);
-  const int64_t o_items = s->dev.round(o_tables + (int64_t)sizeof(QuantConsts) * n_tables);
-  const int64_t o_sse = s->dev.round(o_items + (int64_t)sizeof(WorkItem) * n_items);
-  b.o_sse = o_sse;
-  uint8_t* hb = s->host_base + b.host_off;
-  uint8_t* db = s->dev_base + b.dev_off;
-  Plane* hp = reinterpret_cast<Plane*>(hb + o_planes);
-  QuantConsts* ht = reinterpret_cast<QuantConsts*>(hb + o_tables);
-  WorkItem* hi = reinterpret_cast<WorkItem*>(hb + o_items);
-  uint64_t* dsse = reinterpret_cast<uint64_t*>(db + o_sse);
+  for (const Request& r : b.reqs) n_items += admit_view(r).items;
+  // Admission counted one table per request, so the block fits the region.
+  const MetaLayout ml = meta_layout(b.n_planes, (int64_t)b.reqs.size(), n_items);
+  uint8_t* hb = s->host_meta_of(b.stream);
+  uint8_t* db = s->dev_meta(b.stream);
+  Plane* hp = reinterpret_cast<Plane*>(hb + ml.planes);
+  QuantConsts* ht = reinterpret_cast<QuantConsts*>(hb + ml.tables);
+  WorkItem* hi = reinterpret_cast<WorkItem*>(hb + ml.items);
+  uint64_t* dsse = reinterpret_cast<uint64_t*>(db + ml.sse);
   for (size_t t = 0; t < tables.size(); ++t) fill_quant_consts(tables[t].data(), &ht[t]);
   if (tables.empty()) memset(ht, 0, sizeof(QuantConsts));
-  int k = 0;
-  int64_t it = 0;
+
+  // Descriptors in request order; quantisation scores whole-block planes in the
+  // coefficient domain (as rdct_compress_eval does), the others pixel by pixel.
+  std::vector<Plane> planes;
+  std::vector<bool> coef_err;
   for (size_t ri = 0; ri < b.reqs.size(); ++ri) {
     const Request& r = b.reqs[ri];
-    for (int i = 0; i < r.n; ++i, ++k) {
+    for (int i = 0; i < r.n; ++i) {
       const PlaneSlot& p = r.p[i];
-      hipError_t e = hipMemcpyAsync(s->dev_base + p.dev_off, s->host_base + p.host_off,
-                                    (size_t)p.bytes, hipMemcpyHostToDevice, st);
+      hipError_t e = hipMemcpyAsync(s->plane_ptr(p), s->host_base + p.host_off, (size_t)p.bytes,
+                                    hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return e;
-      Plane P = make_plane(s->dev_base + p.dev_off, p.w, p.h, p.w);
-      P.sse = dsse + k;
+      Plane P = make_plane(s->plane_ptr(p), p.w, p.h, p.w);
+      P.sse = dsse + planes.size();
       P.r = r.r;
       P.keep = keep_bits(r.r);
       P.r_count = 1;
       P.shift = r.shift;
       P.table = table_of[ri];
-      hp[k] = P;
-      for (int t0 = 0; t0 < P.nblocks; t0 += 128) hi[it++] = WorkItem{k, t0};
+      planes.push_back(P);
+      coef_err.push_back(r.sel == SEL_Q && whole_blocks(p.w, p.h));
       b.n_blocks += P.nblocks;
     }
   }
-  hipError_t e = hipMemcpyAsync(db, hb, (size_t)o_sse, hipMemcpyHostToDevice, st);
+  std::vector<int> order;
+  const int n_coef = flagged_first(coef_err, &order);
+  const int n = (int)planes.size();
+  int64_t it = 0;
+  int64_t item0[2] = {0, 0}, count[2] = {0, 0};
+  for (int j = 0; j < n; ++j) {
+    const int g = j < n_coef ? 0 : 1;
+    const int rel = g == 0 ? j : j - n_coef;
+    if (j == n_coef) item0[1] = it;
+    hp[j] = planes[order[j]];
+    for (int t0 = 0; t0 < hp[j].nblocks; t0 += kItemBlocks) {
+      hi[it++] = WorkItem{rel, t0};
+      ++count[g];
+    }
+  }
+  if (n_coef == n) item0[1] = it;
+  hipError_t e = hipMemcpyAsync(db, hb, (size_t)ml.sse, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   if ((e = launch_zero_u64(dsse, b.n_planes, st)) != hipSuccess) return e;
   const int sel = b.reqs[0].sel;
-  const int ev = EV_SPATIAL;
   const int wpg = 4;
-  const int grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2, (n_items + wpg - 1) / wpg));
-  e = launch_batch(sel, CO_NONE, false, ev, reinterpret_cast<Plane*>(db + o_planes),
-                   reinterpret_cast<QuantConsts*>(db + o_tables),
-                   reinterpret_cast<WorkItem*>(db + o_items), (int32_t)n_items, grid, wpg, st);
-  if (e != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(hb + o_sse, dsse, 8 * (size_t)b.n_planes, hipMemcpyDeviceToHost, st)) !=
+  const int evs[2] = {EV_COEF, EV_SPATIAL};
+  const int p0[2] = {0, n_coef};
+  for (int g = 0; g < 2; ++g) {
+    if (count[g] == 0) continue;
+    const int grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)s->n_cu * 2, (count[g] + wpg - 1) / wpg));
+    e = launch_batch(sel, CO_NONE, false, evs[g], reinterpret_cast<Plane*>(db + ml.planes) + p0[g],
+                     reinterpret_cast<QuantConsts*>(db + ml.tables),
+                     reinterpret_cast<WorkItem*>(db + ml.items) + item0[g], (int32_t)count[g], grid,
+                     wpg, st);
+    if (e != hipSuccess) return e;
+  }
+  if ((e = hipMemcpyAsync(hb + ml.sse, dsse, 8 * (size_t)b.n_planes, hipMemcpyDeviceToHost, st)) !=
       hipSuccess)
     return e;
-  if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return e;
-  return hipEventRecord(b.done, st);
+  return hipEventRecord(s->events[b.stream], st);
 }
 
 // Plain path: one plane at a time, synchronously (upload, single-plane launch,
@@ -259,7 +274,7 @@ void run_plain(rdct_server* s, Request& r) {
   uint64_t* dsse = reinterpret_cast<uint64_t*>(s->dev_base);  // first 256 bytes are reserved
   for (int i = 0; i < r.n && status == RDCT_OK; ++i) {
     const PlaneSlot& p = r.p[i];
-    uint8_t* dp = s->dev_base + p.dev_off;
+    uint8_t* dp = s->plane_ptr(p);
     if (hipMemcpyAsync(dp, s->host_base + p.host_off, (size_t)p.bytes, hipMemcpyHostToDevice, st) !=
         hipSuccess) {
       status = RDCT_ERR_HIP;
@@ -288,6 +303,64 @@ void run_plain(rdct_server* s, Request& r) {
   s->cv_done.notify_all();
 }
 
+// Form and launch the next batch on a free stream.  Returns true if the
+// pending queue changed (a batch launched or a request failed).
+bool form_batch(rdct_server* s, int free_stream) {
+  const int n_view = (int)std::min<size_t>(s->pending.size(), (size_t)s->cfg.max_batch_planes);
+  std::vector<AdmitRequest> view(n_view);
+  for (int i = 0; i < n_view; ++i) view[i] = admit_view(s->pending[i]);
+  AdmitLimits lim;
+  lim.max_planes = s->cfg.max_batch_planes;
+  lim.max_requests = std::max<int64_t>(0, s->cfg.max_inflight - s->inflight_reqs);
+  lim.meta_cap = s->meta_cap;
+  lim.sizes = kMetaSizes;
+  std::vector<int64_t[3]> offs(std::max(1, n_view));
+  const int k = admit_batch(view.data(), n_view, &s->dev, lim, offs.data());
+  if (k == 0) {
+    if (!s->inflight.empty() || lim.max_requests == 0) return false;  // wait for room
+    // Nothing in flight and still no room: the submit checks make this
+    // unreachable; fail the request rather than retry it forever.
+    Request r = s->pending.front();
+    s->pending.pop_front();
+    release_request(s, r);
+    complete(s, r, RDCT_ERR_BUDGET, nullptr, s->now_us(), 0);
+    s->st.completed++;
+    s->cv_done.notify_all();
+    return true;
+  }
+  Batch b;
+  b.stream = free_stream;
+  for (int i = 0; i < k; ++i) {
+    Request r = s->pending.front();
+    s->pending.pop_front();
+    for (int p = 0; p < r.n; ++p) r.p[p].dev_off = offs[i][p];
+    b.n_planes += r.n;
+    b.reqs.push_back(r);
+  }
+  b.t_launch = s->now_us();
+  for (Request& r : b.reqs) r.t_launch = b.t_launch;
+  const hipError_t e = launch(s, b);
+  s->st.batches++;
+  s->st.planes += b.n_planes;
+  s->st.blocks += b.n_blocks;
+  if (e != hipSuccess) {
+    // The event was not recorded: complete with an error now.  Work already
+    // queued on the stream is waited for before the planes are reused.
+    (void)hipStreamSynchronize(s->streams[b.stream]);
+    for (Request& r : b.reqs) {
+      complete(s, r, RDCT_ERR_HIP, nullptr, s->now_us(), b.n_planes);
+      release_request(s, r);
+      s->st.completed++;
+    }
+    s->cv_done.notify_all();
+  } else {
+    s->stream_busy[b.stream] = true;
+    s->inflight_reqs += (int64_t)b.reqs.size();
+    s->inflight.push_back(std::move(b));
+  }
+  return true;
+}
+
 void worker_main(rdct_server* s) {
   const bool device_ok = hipSetDevice(s->device) == hipSuccess;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -309,7 +382,7 @@ void worker_main(rdct_server* s) {
   for (;;) {
     // Retire finished batches.
     for (auto bi = s->inflight.begin(); bi != s->inflight.end();) {
-      const hipError_t q = hipEventQuery(bi->done);
+      const hipError_t q = hipEventQuery(s->events[bi->stream]);
       if (q == hipErrorNotReady) {
         ++bi;
         continue;
@@ -318,7 +391,7 @@ void worker_main(rdct_server* s) {
       const int status = q == hipSuccess ? RDCT_OK : RDCT_ERR_HIP;
       const uint64_t* sums =
           status == RDCT_OK
-              ? reinterpret_cast<const uint64_t*>(s->host_base + bi->host_off + bi->o_sse)
+              ? reinterpret_cast<const uint64_t*>(s->host_meta_of(bi->stream) + batch_sse_offset(*bi))
               : nullptr;
       int k = 0;
       for (Request& r : bi->reqs) {
@@ -328,27 +401,25 @@ void worker_main(rdct_server* s) {
         s->inflight_reqs--;
         s->st.completed++;
       }
-      s->dev.release(bi->dev_off, bi->dev_bytes);
-      s->host.release(bi->host_off, bi->host_bytes);
-      (void)hipEventDestroy(bi->done);
       s->stream_busy[bi->stream] = false;
       bi = s->inflight.erase(bi);
       s->cv_done.notify_all();
     }
     if (s->stop && s->inflight.empty()) break;
 
-    bool launched = false;
+    bool progressed = false;
     if (!s->stop && !s->pending.empty()) {
       if (s->cfg.plain) {
         Request r = s->pending.front();
         s->pending.pop_front();
-        // Device copy of the planes.
+        // Device copy of the planes: nothing else holds the arena in this mode
+        // and submit checked that the planes fit it.
         bool ok = true;
         for (int i = 0; i < r.n && ok; ++i) {
           r.p[i].dev_off = s->dev.alloc(r.p[i].bytes);
           ok = r.p[i].dev_off >= 0;
         }
-        if (!ok) {  // cannot happen for a lone request (checked at submit); be safe
+        if (!ok) {
           release_request(s, r);
           complete(s, r, RDCT_ERR_BUDGET, nullptr, s->now_us(), 0);
           s->st.completed++;
@@ -368,81 +439,10 @@ void worker_main(rdct_server* s) {
           free_stream = i;
           break;
         }
-      if (free_stream >= 0) {
-        Batch b;
-        b.stream = free_stream;
-        const int sel = s->pending.front().sel;
-        int64_t items = 0;
-        while (!s->pending.empty()) {
-          Request& r = s->pending.front();
-          if (r.sel != sel) break;
-          if (b.n_planes + r.n > s->cfg.max_batch_planes) break;
-          if (s->inflight_reqs + (int64_t)b.reqs.size() >= s->cfg.max_inflight) break;
-          bool ok = true;
-          for (int i = 0; i < r.n && ok; ++i) {
-            r.p[i].dev_off = s->dev.alloc(r.p[i].bytes);
-            ok = r.p[i].dev_off >= 0;
-          }
-          if (!ok) {
-            for (int i = 0; i < r.n; ++i)
-              if (r.p[i].dev_off >= 0) {
-                s->dev.release(r.p[i].dev_off, r.p[i].bytes);
-                r.p[i].dev_off = -1;
-              }
-            break;
-          }
-          items += request_items(r);
-          b.n_planes += r.n;
-          b.reqs.push_back(r);
-          s->pending.pop_front();
-        }
-        if (!b.reqs.empty()) {
-          const int64_t meta = batch_meta_bytes(b.n_planes, (int)b.reqs.size(), items);
-          b.dev_off = s->dev.alloc(meta);
-          b.host_off = s->host.alloc(meta);
-          if (b.dev_off < 0 || b.host_off < 0) {
-            // Not enough room for the descriptors: give the requests back.
-            if (b.dev_off >= 0) s->dev.release(b.dev_off, meta);
-            if (b.host_off >= 0) s->host.release(b.host_off, meta);
-            for (auto ri = b.reqs.rbegin(); ri != b.reqs.rend(); ++ri) {
-              for (int i = 0; i < ri->n; ++i) {
-                s->dev.release(ri->p[i].dev_off, ri->p[i].bytes);
-                ri->p[i].dev_off = -1;
-              }
-              s->pending.push_front(*ri);
-            }
-          } else {
-            b.dev_bytes = b.host_bytes = meta;
-            b.t_launch = s->now_us();
-            for (Request& r : b.reqs) r.t_launch = b.t_launch;
-            const hipError_t e = launch(s, b);
-            s->stream_busy[b.stream] = true;
-            s->inflight_reqs += (int64_t)b.reqs.size();
-            s->st.batches++;
-            s->st.planes += b.n_planes;
-            s->st.blocks += b.n_blocks;
-            if (e != hipSuccess && !b.done) {
-              // Nothing was recorded: complete with an error now.
-              for (Request& r : b.reqs) {
-                complete(s, r, RDCT_ERR_HIP, nullptr, s->now_us(), b.n_planes);
-                release_request(s, r);
-                s->inflight_reqs--;
-                s->st.completed++;
-              }
-              s->dev.release(b.dev_off, b.dev_bytes);
-              s->host.release(b.host_off, b.host_bytes);
-              s->stream_busy[b.stream] = false;
-              s->cv_done.notify_all();
-            } else {
-              s->inflight.push_back(std::move(b));
-            }
-            launched = true;
-          }
-        }
-      }
+      if (free_stream >= 0) progressed = form_batch(s, free_stream);
     }
     s->st.peak_device_bytes = std::max(s->st.peak_device_bytes, s->dev.in_use());
-    if (launched) continue;
+    if (progressed) continue;
     if (s->inflight.empty())
       s->cv_work.wait(lk, [&] { return s->stop.load() || !s->pending.empty(); });
     else
@@ -462,13 +462,16 @@ void destroy(rdct_server* s) {
     s->cv_work.notify_all();
     s->worker.join();
   }
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
     if (s->streams[i]) {
       (void)hipStreamSynchronize(s->streams[i]);
       (void)hipStreamDestroy(s->streams[i]);
     }
+    if (s->events[i]) (void)hipEventDestroy(s->events[i]);
+  }
   if (s->dev_base) (void)hipFree(s->dev_base);
   if (s->host_base) (void)hipHostFree(s->host_base);
+  if (s->host_meta) (void)hipHostFree(s->host_meta);
   delete s;
 }
 
@@ -494,17 +497,21 @@ rdct_status_t rdct_server_create(const rdct_server_cfg_t* cfg, rdct_server_t** o
     return RDCT_ERR_HIP;
   }
   s->n_cu = device_cu_count();
+  s->meta_cap = meta_region_bytes(s->cfg.budget_bytes);
+  s->plane_base = 256 + (int64_t)s->cfg.n_streams * s->meta_cap;
   // The first 256 bytes of the device budget hold the plain path's error sum.
   if (hipMalloc(&s->dev_base, (size_t)s->cfg.budget_bytes) != hipSuccess ||
-      hipHostMalloc(&s->host_base, (size_t)s->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&s->host_base, (size_t)s->cfg.staging_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&s->host_meta, (size_t)(s->cfg.n_streams * s->meta_cap), hipHostMallocDefault) !=
+          hipSuccess) {
     destroy(s);
     return RDCT_ERR_NO_MEMORY;
   }
-  s->dev.reset(s->cfg.budget_bytes, 256);
-  s->dev.alloc(256);
+  s->dev.reset(s->cfg.budget_bytes - s->plane_base, 256);
   s->host.reset(s->cfg.staging_bytes, 256);
   for (int i = 0; i < s->cfg.n_streams; ++i)
-    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) != hipSuccess) {
       destroy(s);
       return RDCT_ERR_HIP;
     }
@@ -526,7 +533,7 @@ rdct_status_t rdct_server_submit(rdct_server_t* s, const rdct_request_t* req, ui
   r.r = si.r;
   r.shift = si.shift;
   memcpy(r.q, si.q, sizeof(r.q));
-  int64_t dev_need = 0, items = 0, host_need = 0;
+  int64_t dev_need = 0, host_need = 0;
   for (int i = 0; i < r.n; ++i) {
     if ((st = check_plane(req->planes[i], req->width[i], req->height[i], req->pitch[i],
                           kMaxEvalBlocks)) != RDCT_OK)
@@ -536,10 +543,10 @@ rdct_status_t rdct_server_submit(rdct_server_t* s, const rdct_request_t* req, ui
     r.p[i].bytes = plane_dev_bytes(r.p[i].w, r.p[i].h);
     dev_need += s->dev.round(r.p[i].bytes);
     host_need += s->host.round(r.p[i].bytes);
-    items += (rdct_num_blocks(r.p[i].w, r.p[i].h) + 127) / 128;
   }
-  dev_need += s->dev.round(batch_meta_bytes(r.n, 1, items)) + 256;
-  if (dev_need > s->cfg.budget_bytes || host_need > s->cfg.staging_bytes) {
+  // A request that could not run alone is refused now rather than queued forever.
+  if (dev_need > s->dev.size() || host_need > s->host.size() ||
+      request_meta_bytes(admit_view(r), kMetaSizes) > s->meta_cap) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->st.rejected++;
     return RDCT_ERR_BUDGET;

@@ -140,6 +140,16 @@ def _declare_extra(L):
     L.rdct_quality_sse_unit.restype = c_double
     L.rdct_quality_windows.argtypes = [c_int32, c_int32]
     L.rdct_quality_windows.restype = c_int64
+    L.rdct_quality_metrics.argtypes = [P, P, c_int32, c_int32, c_int32, c_int32, P, P]
+    L.rdct_quality_metrics.restype = c_int32
+    L.rdct_psnr_planes.argtypes = [P, c_int32, c_int32, c_int32, P, P, P, P]
+    L.rdct_psnr_planes.restype = c_int32
+    L.rdct_codec_unpack_pairs.argtypes = [P, c_int64, P, P]
+    L.rdct_codec_unpack_pairs.restype = c_int32
+    L.rdct_stream_unit_bytes.argtypes = [c_int32, POINTER(c_int64), POINTER(c_int64)]
+    L.rdct_stream_unit_bytes.restype = c_int32
+    L.rdct_stream.argtypes = [P, P, c_int64, c_int32, c_int32, c_int32, P]
+    L.rdct_stream.restype = c_int32
     L.rdct_quality_plan_create.argtypes = [POINTER(QualityDesc), c_int32, c_int32, c_int32, c_int32,
                                            P, P, POINTER(c_void_p)]
     L.rdct_quality_plan_create.restype = c_int32
@@ -386,7 +396,6 @@ class BatchPlan:
 # ---------------------------------------------------------------------------
 
 T_RDCT, T_DCT, T_SDCT, T_RDCT_CEIL, T_RDCT_FLOOR = range(5)
-UQI_UNIT = 2.0 ** -32
 
 
 def rdct_quality_sweep(src, width, height, pitch, transform, r_first, r_count, sse_out, uqi_out,
@@ -414,13 +423,65 @@ def quality_sweep(img: torch.Tensor, transform: int, r_first: int = 1, r_count: 
     return sse, uqi
 
 
+def _host_array(a, dtype):
+    """A C-contiguous numpy array of `dtype` (host memory) for a host-array call."""
+    import numpy as np
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(c_void_p)
+
+
+def rdct_quality_metrics(sse_raw, uqi_raw, transform, width, height):
+    """(mse, uqi) float64 numpy arrays from one plane's raw sums (host arrays)."""
+    import numpy as np
+    sse = _host_array(sse_raw, np.uint64).reshape(-1)
+    uqi = _host_array(uqi_raw, np.int64).reshape(-1)
+    if sse.size != uqi.size:
+        raise ValueError("sse and uqi differ in length")
+    mse = np.empty(sse.size, dtype=np.float64)
+    mu = np.empty(sse.size, dtype=np.float64)
+    _check(lib().rdct_quality_metrics(_np_ptr(sse), _np_ptr(uqi), sse.size, transform, width,
+                                      height, _np_ptr(mse), _np_ptr(mu)), "rdct_quality_metrics")
+    return mse, mu
+
+
 def quality_metrics(sse_raw, uqi_raw, transform, height, width):
     """MSE and mean UQI (float64 numpy arrays) from raw sums."""
+    return rdct_quality_metrics(sse_raw, uqi_raw, transform, width, height)
+
+
+def rdct_psnr_planes(sse_raw, r_count, mode, widths, heights, mean=False):
+    """PSNR of n planes (n x r_count float64 numpy array) from their raw sums,
+    and with mean=True also the r_count means over the planes."""
     import numpy as np
-    unit = rdct_quality_sse_unit(transform)
-    mse = np.asarray(sse_raw, dtype=np.float64) * unit / (height * width)
-    uqi = np.asarray(uqi_raw, dtype=np.float64) * UQI_UNIT / rdct_quality_windows(width, height)
-    return mse, uqi
+    sse = _host_array(sse_raw, np.uint64).reshape(-1)
+    w = _host_array(widths, np.int32)
+    h = _host_array(heights, np.int32)
+    n = w.size
+    if h.size != n or sse.size != n * r_count:
+        raise ValueError("sizes and sums do not match")
+    out = np.empty(n * r_count, dtype=np.float64)
+    avg = np.empty(r_count, dtype=np.float64) if mean else None
+    _check(lib().rdct_psnr_planes(_np_ptr(sse), n, r_count, mode, _np_ptr(w), _np_ptr(h),
+                                  _np_ptr(out), _np_ptr(avg) if mean else None),
+           "rdct_psnr_planes")
+    out = out.reshape(n, r_count)
+    return (out, avg) if mean else out
+
+
+def rdct_codec_unpack_pairs(words):
+    """(runs, values) int32 numpy arrays of packed pair words."""
+    import numpy as np
+    w = _host_array(words, np.int32).reshape(-1)
+    runs = np.empty(w.size, dtype=np.int32)
+    vals = np.empty(w.size, dtype=np.int32)
+    _check(lib().rdct_codec_unpack_pairs(_np_ptr(w), w.size, _np_ptr(runs), _np_ptr(vals)),
+           "rdct_codec_unpack_pairs")
+    return runs, vals
 
 
 class QualityPlan:
@@ -460,7 +521,7 @@ class QualityPlan:
         mu = np.empty(uqi.shape)
         for i, img in enumerate(self.planes):
             h, w = img.shape
-            mse[i], mu[i] = quality_metrics(sse[i], uqi[i], self.transform, h, w)
+            mse[i], mu[i] = rdct_quality_metrics(sse[i], uqi[i], self.transform, w, h)
         return mse, mu
 
     def close(self):
@@ -521,8 +582,32 @@ class Codec:
         import numpy as np
         torch.cuda.synchronize()
         off = self.offsets.cpu().numpy().astype(np.int64)
-        words = self.packed[:int(off[-1])].cpu().numpy().astype(np.int64) & 0xffffffff
-        runs = words >> 16
-        vals = ((words & 0xffff) ^ 0x8000) - 0x8000
+        runs, vals = rdct_codec_unpack_pairs(self.packed[:int(off[-1])])
         return [list(zip(runs[off[b]:off[b + 1]].tolist(), vals[off[b]:off[b + 1]].tolist()))
                 for b in range(self.nb)]
+
+
+# ---------------------------------------------------------------------------
+# Bandwidth calibration (rdct_stream)
+# ---------------------------------------------------------------------------
+
+STREAM_READ, STREAM_WRITE, STREAM_COPY, STREAM_R1W2, STREAM_R1W6 = range(5)
+
+
+def rdct_stream_unit_bytes(pattern):
+    """(read, written) bytes of one unit of `pattern`."""
+    rb, wb = c_int64(), c_int64()
+    _check(lib().rdct_stream_unit_bytes(pattern, ctypes.byref(rb), ctypes.byref(wb)),
+           "rdct_stream_unit_bytes")
+    return rb.value, wb.value
+
+
+def rdct_stream(src, dst, units, pattern, flags=3, wgs_per_cu=0, stream=None):
+    """Move `units` units of `pattern` from device tensor src to dst (sizes checked)."""
+    rb, wb = rdct_stream_unit_bytes(pattern)
+    if src is not None and src.numel() * src.element_size() < units * rb:
+        raise ValueError("source smaller than the units read")
+    if dst.numel() * dst.element_size() < max(units * wb, 1024):
+        raise ValueError("destination smaller than the units written")
+    _check(lib().rdct_stream(_ptr(src), _ptr(dst), units, pattern, flags, wgs_per_cu,
+                             _stream(stream)), "rdct_stream")

@@ -205,3 +205,39 @@ def test_codec_rejects():
     assert L.rdct_codec_pack(FAKE_DST, FAKE_DST, FAKE_DST, 64, 64, FAKE_DST, None, 10, FAKE_DST,
                              None) == R.ERR_INVALID_ARG
     assert R.rdct_codec_groups(64, 64) == 1 and R.rdct_codec_groups(72, 64) == 2
+
+
+def test_psnr_of_many_planes_matches_single_calls():
+    import numpy as np
+    rng = np.random.default_rng(3)
+    widths, heights = [8, 64, 13], [8, 40, 21]
+    sse = rng.integers(0, 2 ** 40, size=(3, 5)).astype(np.uint64)
+    sse[1, 2] = 0
+    for mode in (R.SEL_ZIGZAG, R.SEL_QUANT):
+        ps, mean = R.rdct_psnr_planes(sse, 5, mode, widths, heights, mean=True)
+        for i in range(3):
+            for j in range(5):
+                assert ps[i, j] == R.rdct_psnr(int(sse[i, j]), mode, widths[i], heights[i])
+        assert np.isinf(mean[2])
+        assert abs(mean[0] - ps[:, 0].mean()) < 1e-12
+    with pytest.raises(RuntimeError):
+        R.rdct_psnr_planes(sse, 5, R.SEL_ZIGZAG, [8, 0, 8], heights)
+
+
+def test_quality_metrics_units():
+    import numpy as np
+    sse = np.array([576 ** 2 * 64, 0], dtype=np.uint64)
+    uqi = np.array([2 ** 32, 2 ** 31], dtype=np.int64)
+    mse, mu = R.rdct_quality_metrics(sse, uqi, R.T_RDCT, 8, 8)
+    assert mse.tolist() == [1.0, 0.0] and mu.tolist() == [1.0, 0.5]
+    mse, mu = R.rdct_quality_metrics(np.array([2 ** 20 * 9]), np.array([2 ** 32 * 4]), R.T_DCT, 9, 9)
+    assert mse[0] == 1.0 / 9 and mu[0] == 1.0
+    with pytest.raises(RuntimeError):
+        R.rdct_quality_metrics(sse, uqi, R.T_RDCT_FLOOR, 8, 8)
+
+
+def test_pair_words_decode():
+    import numpy as np
+    words = np.array([(5 << 16) | 0xfffe, (63 << 16) | 0x7fff, 0x8000, 0], dtype=np.uint32).view(np.int32)
+    runs, vals = R.rdct_codec_unpack_pairs(words)
+    assert runs.tolist() == [5, 63, 0, 0] and vals.tolist() == [-2, 32767, -32768, 0]

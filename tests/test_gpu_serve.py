@@ -153,3 +153,49 @@ def test_replay_trace():
     lat = S.latency_stats(done)
     assert 0 < lat["p50_ms"] <= lat["p99_ms"]
     srv.close()
+
+
+def test_quant_requests_in_mix_equal_alone():
+    # Whole-block planes (scored in the coefficient domain) and planes with
+    # partial blocks (odd 4:2:0 chroma sizes, scored pixel by pixel) share
+    # batches; each plane's sum has the bits it has alone.
+    reqs = small_trace(30, 5)
+    rng = np.random.default_rng(5)
+    sels = [R.select(R.SEL_QUANT, quality=int(q), level_shift=128)
+            for q in rng.integers(10, 91, len(reqs))]
+    shapes = [p.shape for planes, _ in reqs for p in planes]
+    assert any(h % 8 or w % 8 for h, w in shapes) and any(h % 8 == 0 and w % 8 == 0 for h, w in shapes)
+    srv = S.Server(budget_bytes=256 << 20, n_streams=2)
+    for i, ((planes, _), sel) in enumerate(zip(reqs, sels)):
+        srv.submit(planes, sel, tag=i)
+    assert srv.drain(60000) == R.OK
+    got = {}
+    while len(got) < len(reqs):
+        for c in srv.poll(256, wait_us=1000):
+            got[c["tag"]] = c
+    for i, ((planes, _), sel) in enumerate(zip(reqs, sels)):
+        assert got[i]["status"] == R.OK
+        assert got[i]["sse"] == alone(planes, sel), i
+    assert srv.stats()["batches"] < len(reqs)
+    srv.close()
+
+
+def test_metadata_bound_batches_with_a_small_budget():
+    # A 1 MiB budget: each stream's metadata region holds far fewer requests
+    # than are queued, so batches are cut by metadata, and every request still
+    # completes with its own result.
+    srv = S.Server(budget_bytes=1 << 20, staging_bytes=4 << 20, n_streams=2)
+    planes = [synth.render_np(7, 64, 64), synth.render_np(8, 32, 32), synth.render_np(9, 32, 32)]
+    sels = [R.select(R.SEL_QUANT, quality=q, level_shift=128) for q in range(10, 90)]
+    for i, sel in enumerate(sels):
+        srv.submit(planes, sel, tag=i)
+    assert srv.drain(60000) == R.OK
+    got = {}
+    while len(got) < len(sels):
+        for c in srv.poll(256, wait_us=1000):
+            got[c["tag"]] = c
+    for i in (0, 17, 79):
+        assert got[i]["sse"] == alone(planes, sels[i])
+    st = srv.stats()
+    assert st["completed"] == len(sels) and st["batches"] >= 2
+    srv.close()
