@@ -307,6 +307,24 @@ rdct_status_t rdct_codec_pack(const uint16_t* counts, const uint32_t* group_pair
                               uint32_t* offsets, int32_t* packed, int64_t capacity,
                               uint32_t* workspace, void* stream);
 
+/*
+ * rdct_codec_pack without a caller workspace, for callers that cannot allocate
+ * or pass scratch memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results as
+ * rdct_codec_pack minus `workspace`: the chunk prefixes go to a fixed device
+ * array of the library's own (256 KiB per GPU, held until the process ends),
+ * which covers the largest plane the codec accepts (2^22 blocks); larger
+ * planes return UNSUPPORTED.  Allocates nothing.  Every call on one GPU uses
+ * that GPU's one array, so calls that overlap on one GPU (two streams, or two
+ * host threads) race and must be serialised by the caller; nothing in the
+ * array needs to start at zero.  The first call on a device looks the array's
+ * address up.  Errors: INVALID_ARG, UNSUPPORTED (size), HIP.
+ */
+rdct_status_t rdct_codec_pack_noalloc(const uint16_t* counts, const uint32_t* group_pairs,
+                                      const int32_t* slots, int32_t width, int32_t height,
+                                      uint32_t* offsets, int32_t* packed, int64_t capacity,
+                                      void* stream);
+
 /* Decode n pair words of the packed stream (HOST arrays): run_out[i] = word >> 16,
    value_out[i] = the signed 16-bit low half.  Errors: INVALID_ARG (null arrays
    with n > 0, n < 0). */

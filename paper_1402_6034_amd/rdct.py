@@ -133,6 +133,8 @@ def _declare_extra(L):
     L.rdct_codec_encode.restype = c_int32
     L.rdct_codec_pack.argtypes = [P, P, P, c_int32, c_int32, P, P, c_int64, P, P]
     L.rdct_codec_pack.restype = c_int32
+    L.rdct_codec_pack_noalloc.argtypes = [P, P, P, c_int32, c_int32, P, P, c_int64, P]
+    L.rdct_codec_pack_noalloc.restype = c_int32
     L.rdct_quality_sweep.argtypes = [P, c_int32, c_int32, c_int64, c_int32, c_int32, c_int32, P, P,
                                      P]
     L.rdct_quality_sweep.restype = c_int32
