@@ -42,6 +42,9 @@ KERNEL_SOURCES = {
     "quality": (_CSRC + "rdct_quality.hip", _CSRC + "rdct_quality_api.cpp",
                 _CSRC + "rdct_transforms.cpp"),
     "codec": (_CSRC + "rdct_codec.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_codec_api.cpp"),
+    "inverse": (_CSRC + "rdct_kernels.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_api.cpp"),
+    "single": (_CSRC + "rdct_kernels.hip", _CSRC + "rdct_device.h", _CSRC + "rdct_api.cpp"),
+    "stream": (_CSRC + "rdct_stream.hip", _CSRC + "rdct_device.h"),
 }
 
 
@@ -214,6 +217,71 @@ class FrameQuant:
                           "forward + exact quantisation"}
 
 
+class InverseFrame:
+    """rdct_inverse of one 8192 x 8192 frame's quality-50 quantised int16
+    coefficients back to float32 pixels (float64 dequantisation and transposed
+    transform, level shift added back).  Four buffer sets rotate so the 256 MB
+    last-level cache never holds the next launch's data."""
+    name = "inverse-frame-8192-q50-i16-f32"
+    workload_key = "inverse"
+    dtype = "int16+f64"
+    sets = 4
+
+    def __init__(self, size=8192):
+        import torch
+        from paper_1402_6034_amd import rdct as R, synth
+        self.R = R
+        self.size = size
+        self.nb = (size // 8) ** 2
+        log(f"[bench] rendering {size}x{size} frame")
+        frame = synth.render(0, size, size, device="cuda")
+        self.sel = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+        q = torch.empty((self.nb, 64), dtype=torch.int16, device="cuda")
+        R.forward(frame, self.sel, R.COEF_I16, out=q)
+        del frame
+        self.coefs = [q] + [q.clone() for _ in range(self.sets - 1)]
+        self.recons = [torch.empty((size, size), dtype=torch.float32, device="cuda")
+                       for _ in range(self.sets)]
+        self.i = 0
+
+    def launch(self, i=None):
+        k = self.i if i is None else i % self.sets
+        self.R.inverse(self.coefs[k], self.size, self.size, self.sel, self.R.COEF_I16,
+                       out=self.recons[k])
+        self.i = (self.i + 1) % self.sets
+
+    kernel_launch = launch
+
+    def step(self):
+        self.launch()
+
+    blocks_per_step = property(lambda self: self.nb)
+    bytes_per_block = 128 + 256
+
+    def config(self):
+        return {"workload": self.name, "frame": [self.size, self.size], "blocks": self.nb,
+                "quality": 50, "coef": "int16", "recon": "float32", "level_shift": 128}
+
+    def cpu_baseline(self, budget_s):
+        import numpy as np
+        import oracle as O
+        q = self.coefs[0].cpu().numpy().astype(np.int64).reshape(self.size // 8, self.size // 8, 8, 8)
+        qt = O.quant_table(50)
+        rows = 64  # block rows per band
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget_s:
+            band = q[(n * rows) % (self.size // 8):][:rows]
+            O.inverse_orth(O.dequantize(band, qt))
+            n += 1
+        dt = time.perf_counter() - t0
+        blocks = n * rows * (self.size // 8)
+        return {"value": blocks / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
+                "kind": "oracle",
+                "sample": f"{n} bands of {rows} block rows ({blocks} blocks): dequantise and "
+                          "float64 inverse"}
+
+
 class SumsPipe:
     """Read-back of a plan's error sums for steps run two deep.  submit(slot)
     copies the sums into device buffer `slot` on the launch stream (a small
@@ -336,7 +404,7 @@ class RetentionSweep:
                 "r": [1, 45], "coef": "int32", "layout": LAYOUT_NAME[t.layout],
                 "kernel_launches_per_step": 1 if t.layout == 2 else 2,
                 "waves_per_wg": t.waves_per_wg, "wgs_per_cu": t.wgs_per_cu,
-                "graph": bool(t.use_graph)}
+                "xcd_ranges": bool(t.xcd_ranges), "graph": bool(t.use_graph)}
 
     def plain(self, steps=3):
         """The same sweep as one rdct_compress_eval launch per plane."""
@@ -576,7 +644,7 @@ class RaggedBatch:
         if autotune:
             t = self.plan.autotune(reps=3)
             log(f"[bench] tuned geometry: {LAYOUT_NAME[t.layout]}, {t.waves_per_wg} waves/WG x "
-                f"{t.wgs_per_cu} WGs/CU")
+                f"{t.wgs_per_cu} WGs/CU, XCD ranges {t.xcd_ranges}")
         self.px = sum(it.height * it.width for it in self.items)
         self.psnr = None
 
@@ -613,8 +681,31 @@ class RaggedBatch:
         return {"workload": self.name, "planes": len(self.items), "blocks": self.nb,
                 "pixels": self.px, "coef": "int16", "recon": "float32", "level_shift": 128,
                 "layout": LAYOUT_NAME[t.layout], "waves_per_wg": t.waves_per_wg,
-                "wgs_per_cu": t.wgs_per_cu,
+                "wgs_per_cu": t.wgs_per_cu, "xcd_ranges": bool(t.xcd_ranges),
                 "graph": bool(t.use_graph)}
+
+    def tuning_table(self, reps=10):
+        """Every geometry the autotuner considers, plus hipGraph replay of each,
+        timed on this plan (HIP events over `reps` back-to-back runs, median of
+        three rounds); the plan keeps its tuned geometry afterwards."""
+        R = self.R
+        keep = self.plan.tuning
+        cands = []
+        for wpg in (1, 2, 4):
+            for waves in (2, 4, 8, 12, 16):
+                if waves % wpg == 0:
+                    for xcd in (0, 1):
+                        cands.append((wpg, waves // wpg, R.LAYOUT_STRIDED, xcd))
+            cands.append((wpg, 1, R.LAYOUT_PER_PLANE, 0))
+        rows = []
+        for wpg, wpc, lay, xcd in cands:
+            for graph in (0, 1):
+                self.plan.set_tuning(R.Tuning(wpg, wpc, graph, lay, xcd))
+                ms = sorted(event_time_ms(lambda i: self.plan.run(), reps) for _ in range(3))[1]
+                rows.append({"layout": LAYOUT_NAME[lay], "waves_per_wg": wpg, "wgs_per_cu": wpc,
+                             "xcd_ranges": bool(xcd), "graph": bool(graph), "ms": round(ms, 4)})
+        self.plan.set_tuning(keep)
+        return sorted(rows, key=lambda r: r["ms"])
 
     def plain(self, steps=2):
         """Same planes through the plain path: one rdct_compress_eval launch per plane."""
@@ -643,20 +734,30 @@ class RaggedBatch:
                 "identical_sse": same}
 
     def cpu_baseline(self, budget_s):
+        """The oracle on planes taken in a seeded random order (so the sample has
+        the batch's size mix) until the budget is spent; host copies are made
+        before the clock starts."""
+        import numpy as np
         import oracle as O
+        order = np.random.default_rng(1).permutation(len(self.items))
         t0 = time.perf_counter()
         blocks = n = 0
-        order = sorted(range(len(self.items)), key=lambda k: self.items[k].height * self.items[k].width)
-        while time.perf_counter() - t0 < budget_s and n < len(order):
-            it = self.items[order[n]]
-            O.quant_eval(self.imgs[order[n]].cpu().numpy(), O.quant_table(it.quality))
+        spent = 0.0
+        while spent < budget_s and n < len(order):
+            k = int(order[n])
+            it = self.items[k]
+            img = self.imgs[k].cpu().numpy()
+            t1 = time.perf_counter()
+            O.quant_eval(img, O.quant_table(it.quality))
+            spent += time.perf_counter() - t1
             blocks += (it.height // 8) * (it.width // 8)
             n += 1
-        dt = time.perf_counter() - t0
-        return {"value": blocks / dt / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
+        mean_all = self.nb / len(self.items)
+        return {"value": blocks / spent / 1e6, "unit": "Mblocks/s", "cores": _oracle_threads(),
                 "kind": "oracle",
-                "sample": f"the {n} smallest of the 1000 planes ({blocks} blocks), forward + "
-                          "exact quantisation + float64 inverse + SSE"}
+                "sample": f"{n} of the 1000 planes in a seeded random order ({blocks} blocks, "
+                          f"{blocks / max(n, 1):.0f} per plane against {mean_all:.0f} over the "
+                          "batch), forward + exact quantisation + float64 inverse + SSE"}
 
 
 class SingleImage:
@@ -764,6 +865,7 @@ class StreamCalibration:
                             for _ in range(self.sets[p])]
         self.results = []
         self.best = {}
+        self.no_sweep = False
 
     def run_case(self, p, flags, wpc, reps=20):
         import torch
@@ -780,11 +882,11 @@ class StreamCalibration:
 
     def sweep(self):
         for p in self.units:
-            for flags in range(4):
+            for flags in range(8):
                 for wpc in (0, 2, 4, 8):
                     ms, gbs = self.run_case(p, flags, wpc)
                     row = {"pattern": STREAM_PATTERNS[p][0], "nt_loads": bool(flags & 1),
-                           "nt_stores": bool(flags & 2),
+                           "nt_stores": bool(flags & 2), "xcd_ranges": bool(flags & 4),
                            "grid": "one unit per wave" if wpc == 0 else f"{wpc} WGs/CU persistent",
                            "ms": round(ms, 5), "GB/s": round(gbs, 1)}
                     self.results.append(row)
@@ -794,14 +896,15 @@ class StreamCalibration:
                     log(f"[bench] stream {row}")
 
     def launch(self, i=0):
-        """The 1:2 mix at the frame's size, nontemporal, one unit per wave."""
+        """The 1:2 mix at the frame's size: regular loads, nontemporal stores, two
+        persistent workgroups per CU (the fastest 1:2 form measured)."""
         src, dst = self.bufs[3][i % self.sets[3]]
-        self.R.rdct_stream(src, dst, self.units[3], 3, 3, 0)
+        self.R.rdct_stream(src, dst, self.units[3], 3, 2, 2)
 
     kernel_launch = launch
 
     def step(self):
-        if not self.results:
+        if not self.results and not self.no_sweep:
             self.sweep()
         self.launch()
 
@@ -878,7 +981,7 @@ def serving_leg(n_requests, rate_hz=2000.0, pool=3, budget=8 << 30):
 
 WORKLOADS = {"frame": FrameQuant, "sweep": RetentionSweep, "ragged": RaggedBatch,
              "quality": QualitySweep, "codec": CodecFrame, "single": SingleImage,
-             "stream": StreamCalibration}
+             "stream": StreamCalibration, "inverse": InverseFrame}
 
 
 def _pool_worker(job):
@@ -935,6 +1038,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ragged", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-plane comparison")
+    ap.add_argument("--tuning-table", action="store_true",
+                    help="ragged: time every geometry of the autotuner with and without graph "
+                         "replay and add the table to the line")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="stream: time only the 1:2 kernel (no sweep of every variant)")
     ap.add_argument("--no-extras", action="store_true",
                     help="ragged: skip the frame and single-plane figures added to the line")
     ap.add_argument("--no-autotune", action="store_true",
@@ -981,6 +1089,8 @@ def main():
         wl = QualitySweep(planes_cache=args.planes_cache)
     else:
         wl = WORKLOADS[args.workload]()
+    if args.workload == "stream":
+        wl.no_sweep = args.no_sweep
 
     for _ in range(args.warmup):
         wl.step()
@@ -1041,6 +1151,9 @@ def main():
                                   "instructions_per_launch": valu}
 
     extras = {}
+    if args.workload == "ragged" and args.tuning_table:
+        log("[bench] tuning table")
+        extras["tuning_table"] = wl.tuning_table()
     if args.workload == "ragged" and not args.no_extras:
         # The other configurations' headline figures beside the default line:
         # the 8192^2 quantisation frame (its kernel against the HBM peak) and one
@@ -1078,6 +1191,10 @@ def main():
             cpu = wl.cpu_baseline(args.cpu_budget)
 
     value = wl.blocks_per_step / (ms * 1e-3) / 1e6
+    unit = "Mblocks/s"
+    if args.workload == "stream":
+        # The calibration moves bytes, not blocks: its value is the 1:2 kernel's rate.
+        value, unit = roofline["achieved"], "GB/s"
     plain = None
     if hasattr(wl, "plain") and not args.no_plain:
         log("[bench] timing the plain one-launch-per-plane path")
@@ -1088,7 +1205,7 @@ def main():
         log("[bench] serving leg")
         serving = serving_leg(args.serve_requests)
 
-    out = {"metric": METRIC, "value": round(value, 3), "unit": "Mblocks/s", "n_gpus": 1,
+    out = {"metric": METRIC, "value": round(value, 3), "unit": unit, "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": wl.dtype, "data": "synthetic", "config": wl.config(),

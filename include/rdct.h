@@ -199,6 +199,10 @@ typedef struct {
   int32_t use_graph;       /* 1: runs replay a captured hipGraph; 0: plain launches
                               (the default with a NULL tuning: measured faster)      */
   int32_t layout;          /* rdct_layout_t                                         */
+  int32_t xcd_ranges;      /* STRIDED: 1 = workgroups remapped so that each of the
+                              eight XCDs (each with its own L2) takes a contiguous
+                              range of work items, so neighbouring items share an
+                              L2; 0 = the hardware's round-robin order              */
 } rdct_tuning_t;
 
 typedef struct rdct_batch_plan rdct_batch_plan_t;
@@ -246,6 +250,12 @@ rdct_status_t rdct_batch_plan_create_sweep(const rdct_plane_desc_t* planes, int3
    replay it.  Runs of one plan must not overlap (on two streams at once): they
    share the plan's outputs. */
 rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
+
+/* Run the plan with this geometry from now on (every field given, none taken
+   from the cache; not stored in the cache).  Errors: INVALID_ARG (not a valid
+   geometry: waves_per_wg 1, 2 or 4, wgs_per_cu 1..16, a known layout,
+   xcd_ranges 0 or 1). */
+rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tuning_t* tuning);
 
 /* Blocks and work items of a plan, and the geometry it runs with (any pointer
    may be NULL). */
@@ -526,7 +536,8 @@ rdct_status_t rdct_stream_unit_bytes(int32_t pattern, int64_t* read_bytes, int64
  * are read against.  Each wave instruction reads or writes 1 KiB (16 bytes per
  * lane).  src holds units * read bytes; dst holds units * written bytes (at
  * least 1 KiB for RDCT_STREAM_READ, where it is written only for one value of
- * the data).  flags: bit 0 = nontemporal loads, bit 1 = nontemporal stores.
+ * the data).  flags: bit 0 = nontemporal loads, bit 1 = nontemporal stores,
+ * bit 2 = workgroups remapped so that each XCD takes a contiguous range.
  * wgs_per_cu: 0 = one unit per wave (the grid covers the units), else that many
  * persistent 4-wave workgroups per compute unit (1..32) stride over them.
  * Asynchronous on `stream`; no allocation.

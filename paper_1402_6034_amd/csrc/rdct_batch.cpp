@@ -107,7 +107,8 @@ hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t
                        p->d_first + g.plane0);
     } else {
       e = launch_batch(p->sel, p->co, p->recon, g.ev, p->d_planes + g.plane0, p->d_tables,
-                       p->d_items + g.item0, g.n_items, grid_of(p, g, t), t.waves_per_wg, s);
+                       p->d_items + g.item0, g.n_items, grid_of(p, g, t), t.waves_per_wg, s,
+                       nullptr, t.xcd_ranges);
     }
     if (e != hipSuccess) return e;
   }
@@ -287,12 +288,14 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   // the host on the same stream stalled (537 against 81 us per run and copy).
   t.use_graph = 0;
   t.layout = RDCT_LAYOUT_STRIDED;
+  t.xcd_ranges = 0;
   rdct_tuning_t cached;
   if (tune_cache_lookup(p->key, &cached)) {
     rdct_tuning_t c = t;
     c.waves_per_wg = cached.waves_per_wg;
     c.wgs_per_cu = cached.wgs_per_cu;
     c.layout = cached.layout;
+    c.xcd_ranges = cached.xcd_ranges;
     if (valid_tuning(c)) t = c;
   }
   if (tuning) {
@@ -300,6 +303,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     if (tuning->wgs_per_cu) t.wgs_per_cu = tuning->wgs_per_cu;
     if (tuning->layout) t.layout = tuning->layout;
     t.use_graph = tuning->use_graph ? 1 : 0;
+    t.xcd_ranges = tuning->xcd_ranges;
   }
   if (!valid_tuning(t)) {
     delete p;
@@ -362,6 +366,15 @@ rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream) {
   return hipGraphLaunch(plan->exec, s) == hipSuccess ? RDCT_OK : RDCT_ERR_HIP;
 }
 
+rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tuning_t* tuning) {
+  if (!plan || !tuning || !valid_tuning(*tuning)) return RDCT_ERR_INVALID_ARG;
+  rdct_tuning_t t = *tuning;
+  t.use_graph = t.use_graph ? 1 : 0;
+  plan->tuning = t;
+  plan->graph_ready = false;  // re-captured on the next run when use_graph
+  return RDCT_OK;
+}
+
 rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
                                    int32_t* n_items, rdct_tuning_t* used) {
   if (!plan) return RDCT_ERR_INVALID_ARG;
@@ -378,21 +391,25 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RDCT_ERR_HIP;
   // Candidates: the strided layout over waves per workgroup x resident waves
-  // per CU, and the per-plane layout over waves per workgroup.
+  // per CU x XCD ranges, and the per-plane layout over waves per workgroup.
   std::vector<rdct_tuning_t> cands;
   for (int wpg : {1, 2, 4}) {
     for (int waves : {2, 4, 8, 12, 16}) {
       if (waves % wpg) continue;
-      rdct_tuning_t t = plan->tuning;
-      t.layout = RDCT_LAYOUT_STRIDED;
-      t.waves_per_wg = wpg;
-      t.wgs_per_cu = waves / wpg;
-      cands.push_back(t);
+      for (int xcd : {0, 1}) {
+        rdct_tuning_t t = plan->tuning;
+        t.layout = RDCT_LAYOUT_STRIDED;
+        t.waves_per_wg = wpg;
+        t.wgs_per_cu = waves / wpg;
+        t.xcd_ranges = xcd;
+        cands.push_back(t);
+      }
     }
     rdct_tuning_t t = plan->tuning;
     t.layout = RDCT_LAYOUT_PER_PLANE;
     t.waves_per_wg = wpg;
     t.wgs_per_cu = 1;
+    t.xcd_ranges = 0;
     cands.push_back(t);
   }
   float best_us = 1e30f;

@@ -178,6 +178,16 @@ __device__ __forceinline__ int pixel(const uint32_t (&w)[16], int i, int j) {
 }
 
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup b runs on XCD
+// b % 8), and each XCD has its own L2.  The remap gives each XCD a contiguous
+// range of logical workgroup indices, so neighbouring work lands in one L2:
+// bijective on [0, 8 * (G / 8)), the identity on the last G % 8 workgroups.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int per = G >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -48,7 +48,8 @@ inline rdct_status_t check_plane_dims(const void* src, int32_t w, int32_t h, int
 inline bool valid_tuning(const rdct_tuning_t& t) {
   return (t.waves_per_wg == 1 || t.waves_per_wg == 2 || t.waves_per_wg == 4) &&
          t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16 &&
-         (t.layout == RDCT_LAYOUT_STRIDED || t.layout == RDCT_LAYOUT_PER_PLANE);
+         (t.layout == RDCT_LAYOUT_STRIDED || t.layout == RDCT_LAYOUT_PER_PLANE) &&
+         (t.xcd_ranges == 0 || t.xcd_ranges == 1);
 }
 
 // Work list of planes 0 .. n-1 (nblocks[i] blocks each): plane i's items are

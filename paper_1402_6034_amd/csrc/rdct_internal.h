@@ -125,7 +125,7 @@ hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes
                         const QuantConsts* tables,
                         const WorkItem* items, int32_t n_items, int32_t grid,
                         int32_t waves_per_wg, hipStream_t stream,
-                        const int32_t* first = nullptr);
+                        const int32_t* first = nullptr, int xcd = 0);  // xcd: see xcd_remap
 
 // Compute units of the current device (looked up on every call).
 int device_cu_count();

@@ -758,7 +758,8 @@ template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
                                                   const WorkItem* __restrict__ items,
-                                                  int n_items, const int* __restrict__ first) {
+                                                  int n_items, const int* __restrict__ first,
+                                                  int xcd) {
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -823,7 +824,8 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
     return;
   }
 
-  int it = blockIdx.x * wpg + wave;
+  const int b = xcd ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  int it = b * wpg + wave;
   if (it >= n_items) return;
   // The wave's error parts accumulate while its items stay in one plane and are
   // written when the plane changes: a large plane gets one atomic per wave
@@ -847,16 +849,17 @@ template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 2) void k_batch(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
                                                   const WorkItem* __restrict__ items, int n_items,
-                                                  const int* __restrict__ first) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first);
+                                                  const int* __restrict__ first, int xcd) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ planes,
                                                     const QuantConsts* __restrict__ tables,
                                                     const WorkItem* __restrict__ items,
-                                                    int n_items, const int* __restrict__ first) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first);
+                                                    int n_items, const int* __restrict__ first,
+                                                    int xcd) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd);
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,7 +1016,7 @@ static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg,
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
                                  const WorkItem* items, int n_items, const int* first,
-                                 int grid, int wpg, hipStream_t s) {
+                                 int grid, int wpg, int xcd, hipStream_t s) {
   static_assert(Stage<CO>::wave_bytes % 8 == 0 && kReconStageBytes % 8 == 0,
                 "stages keep the per-plane sums area 8-byte aligned");
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
@@ -1021,10 +1024,10 @@ static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
                      (first != nullptr && EV != EV_NONE ? (size_t)wpg * 64 * 8 : 0);
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items, first);
+                       tables, items, n_items, first, xcd);
   else
     hipLaunchKernelGGL((k_batch<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items, first);
+                       tables, items, n_items, first, xcd);
   return hipGetLastError();
 }
 
@@ -1073,9 +1076,9 @@ hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
                         const QuantConsts* tables, const WorkItem* items,
                         int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s,
-                        const int32_t* first) {
+                        const int32_t* first, int xcd) {
   if (n_items <= 0) return hipSuccess;
-  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, first, grid, wpg, s)
+  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, first, grid, wpg, xcd, s)
 }
 
 hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height, int32_t r,

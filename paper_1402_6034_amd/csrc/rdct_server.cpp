@@ -443,10 +443,17 @@ void worker_main(rdct_server* s) {
     }
     s->st.peak_device_bytes = std::max(s->st.peak_device_bytes, s->dev.in_use());
     if (progressed) continue;
-    if (s->inflight.empty())
+    if (s->inflight.empty()) {
       s->cv_work.wait(lk, [&] { return s->stop.load() || !s->pending.empty(); });
-    else
-      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    } else {
+      // Batches in flight: poll their events again at once.  A timed wait
+      // sleeps for at least the kernel's timer slack (tens of microseconds),
+      // which every request in flight would wait on; yielding only gives the
+      // core to other runnable threads (submitters, pollers).
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
   }
 }
 

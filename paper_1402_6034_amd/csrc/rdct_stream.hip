@@ -15,9 +15,11 @@ namespace rdct {
 
 template <bool NTL, bool NTS, int RL, int WL>
 __global__ __launch_bounds__(256) void k_stream(const u32x4* __restrict__ src,
-                                                u32x4* __restrict__ dst, int64_t n_units) {
+                                                u32x4* __restrict__ dst, int64_t n_units,
+                                                int xcd) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int b = xcd ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int64_t wave = (int64_t)b * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   uint32_t acc = 0;
   for (int64_t u = wave; u < n_units; u += n_waves) {
@@ -53,21 +55,23 @@ __global__ __launch_bounds__(256) void k_stream(const u32x4* __restrict__ src,
 }
 
 template <bool NTL, bool NTS, int RL, int WL>
-static hipError_t launch_stream_t(const void* src, void* dst, int64_t units, int grid,
+static hipError_t launch_stream_t(const void* src, void* dst, int64_t units, int grid, int xcd,
                                   hipStream_t s) {
   hipLaunchKernelGGL((k_stream<NTL, NTS, RL, WL>), dim3(grid), dim3(256), 0, s,
-                     reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), units);
+                     reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), units,
+                     xcd);
   return hipGetLastError();
 }
 
 template <int RL, int WL>
 static hipError_t launch_stream_mix(const void* src, void* dst, int64_t units, int grid,
                                     int flags, hipStream_t s) {
+  const int xcd = (flags >> 2) & 1;
   switch (flags & 3) {
-    case 0: return launch_stream_t<false, false, RL, WL>(src, dst, units, grid, s);
-    case 1: return launch_stream_t<true, false, RL, WL>(src, dst, units, grid, s);
-    case 2: return launch_stream_t<false, true, RL, WL>(src, dst, units, grid, s);
-    default: return launch_stream_t<true, true, RL, WL>(src, dst, units, grid, s);
+    case 0: return launch_stream_t<false, false, RL, WL>(src, dst, units, grid, xcd, s);
+    case 1: return launch_stream_t<true, false, RL, WL>(src, dst, units, grid, xcd, s);
+    case 2: return launch_stream_t<false, true, RL, WL>(src, dst, units, grid, xcd, s);
+    default: return launch_stream_t<true, true, RL, WL>(src, dst, units, grid, xcd, s);
   }
 }
 
@@ -90,7 +94,7 @@ rdct_status_t rdct_stream_unit_bytes(int32_t pattern, int64_t* read_bytes, int64
 
 rdct_status_t rdct_stream(const void* src, void* dst, int64_t units, int32_t pattern,
                           int32_t flags, int32_t wgs_per_cu, void* stream) {
-  if (pattern < 0 || pattern > 4 || units < 0 || flags < 0 || flags > 3 || wgs_per_cu < 0 ||
+  if (pattern < 0 || pattern > 4 || units < 0 || flags < 0 || flags > 7 || wgs_per_cu < 0 ||
       wgs_per_cu > 32)
     return RDCT_ERR_INVALID_ARG;
   if ((kStreamRL[pattern] > 0 && (!src || !aligned(src, 16))) || !dst || !aligned(dst, 16))

@@ -100,7 +100,7 @@ class PlaneDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """rdct_tuning_t."""
     _fields_ = [("waves_per_wg", c_int32), ("wgs_per_cu", c_int32), ("use_graph", c_int32),
-                ("layout", c_int32)]
+                ("layout", c_int32), ("xcd_ranges", c_int32)]
 
 
 class QualityDesc(ctypes.Structure):
@@ -121,6 +121,8 @@ def _declare_extra(L):
     L.rdct_batch_run.argtypes = [P, P]
     L.rdct_batch_run.restype = c_int32
     L.rdct_batch_plan_info.argtypes = [P, POINTER(c_int64), POINTER(c_int32), POINTER(Tuning)]
+    L.rdct_batch_plan_set_tuning.argtypes = [P, POINTER(Tuning)]
+    L.rdct_batch_plan_set_tuning.restype = c_int32
     L.rdct_batch_plan_info.restype = c_int32
     L.rdct_batch_autotune.argtypes = [P, c_int32, P, POINTER(Tuning)]
     L.rdct_batch_autotune.restype = c_int32
@@ -376,6 +378,11 @@ class BatchPlan:
 
     def run(self, stream=None):
         rdct_batch_run(self.handle, stream)
+
+    def set_tuning(self, tuning):
+        _check(lib().rdct_batch_plan_set_tuning(self.handle, ctypes.byref(tuning)),
+               "rdct_batch_plan_set_tuning")
+        self.tuning = rdct_batch_plan_info(self.handle)[2]
 
     def autotune(self, reps=5, stream=None):
         self.tuning = rdct_batch_autotune(self.handle, reps, stream)

@@ -241,3 +241,8 @@ def test_pair_words_decode():
     words = np.array([(5 << 16) | 0xfffe, (63 << 16) | 0x7fff, 0x8000, 0], dtype=np.uint32).view(np.int32)
     runs, vals = R.rdct_codec_unpack_pairs(words)
     assert runs.tolist() == [5, 63, 0, 0] and vals.tolist() == [-2, 32767, -32768, 0]
+
+
+def test_set_tuning_rejects_a_null_plan_and_invalid_geometry():
+    t = R.Tuning(1, 4, 0, R.LAYOUT_STRIDED, 0)
+    assert R.lib().rdct_batch_plan_set_tuning(None, ctypes.byref(t)) == R.ERR_INVALID_ARG

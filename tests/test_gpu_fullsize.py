@@ -2,7 +2,8 @@
 bench.py times: sampled blocks against the oracle, block by block, and
 size-independent properties (batch == single plane, sums over blocks).
 
-  * frame   8192 x 8192, quality 50, int16 q (single-plane kernel)
+  * frame   8192 x 8192, quality 50, int16 q (single-plane kernel), and its
+            inverse back to float32 pixels
   * ragged  the 1000-plane batch (persistent kernel, default geometry and the
             autotuned one), int16 q + float32 reconstruction + per-plane SSE
   * sweep   256 planes of 512 x 512, keep r = 1..45 (one batch launch, and
@@ -54,6 +55,24 @@ def test_frame_quantise_sampled(frame):
     want, _ = oracle_q_blocks(img_np, idx, 50)
     got = host(q[torch.from_numpy(idx).to(DEV)]).astype(np.int64)
     assert np.array_equal(got, want.reshape(-1, 64))
+
+
+def test_inverse_frame_sampled(frame):
+    # rdct_inverse as the inverse workload times it: the frame's Q50 int16 q back
+    # to float32 pixels (staged row stores), sampled blocks against the oracle's
+    # float64 dequantise + C_orth^T Z C_orth + 128, within 1e-4.
+    img, img_np = frame
+    sel = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+    q = R.forward(img, sel, R.COEF_I16)
+    rec = R.inverse(q, 8192, 8192, sel, R.COEF_I16)
+    nb = 1024 * 1024
+    idx = sample_idx(np.random.default_rng(4), nb, 3000)
+    want_q, _ = oracle_q_blocks(img_np, idx, 50)
+    want = O.inverse_orth(O.dequantize(want_q, O.quant_table(50))) + 128
+    by, bx = idx // 1024, idx % 1024
+    r = host(rec)
+    got = np.stack([r[8 * y:8 * y + 8, 8 * x:8 * x + 8] for y, x in zip(by, bx)])
+    assert float(np.max(np.abs(got - want))) <= 1e-4
 
 
 def test_codec_frame_sampled(frame):
