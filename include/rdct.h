@@ -371,8 +371,10 @@ typedef enum {
  *               Q = [2 s_xy / (s_x^2 + s_y^2)] [2 xbar ybar / (xbar^2 + ybar^2)]
  *               (a factor whose denominator is 0 counts as 1; so that float64
                noise in exactly flat blocks cannot decide it, a reconstruction
-               window with variance <= 2^-24 grey levels^2 counts as flat and a
-               window mean of magnitude <= 2^-24 as 0), as int64 in units
+               window with variance <= 2^-32 grey levels^2 counts as flat and a
+               window mean of magnitude <= 2^-32 as 0; both bounds lie below
+               the resolution of the RDCT and SDCT integer numerators, so for
+               those only exactly flat or zero-mean windows qualify), as int64 in units
  *               of 2^-32 (float64 per tile, then rounded); mean UQI =
  *               uqi_out * 2^-32 / rdct_quality_windows(width, height).  For RDCT and
  *               SDCT the window sums are exact integers, so only each window's

@@ -33,10 +33,15 @@ Readings where the paper is silent (each is listed in the design notes):
     DC term and is reconstructed exactly in real arithmetic, but the float64
     transforms leave ~1e-13 of noise in it; in a flat or all-zero area that noise
     alone would then set f_s or f_m.  So, in grey levels: a reconstruction window
-    whose variance (over N = 64 pixels) is at most 2^-24 counts as flat (s_y^2 =
-    s_xy = 0), a window mean |ybar| <= 2^-24 counts as 0, and a flat pixel window
-    has s_xy = 0.  Float64 noise stays three orders of magnitude below these
-    bounds.
+    whose variance (over N = 64 pixels) is at most 2^-32 counts as flat (s_y^2 =
+    s_xy = 0), a window mean |ybar| <= 2^-32 counts as 0, and a flat pixel window
+    has s_xy = 0.  Float64 noise (~1e-13 per pixel) stays more than three orders
+    of magnitude below these bounds, and the bounds stay below the resolution of
+    the integer-numerator reconstructions (a window whose numerators y d are not
+    all equal has N^2 d^2 var >= N - 1, i.e. var >= 63 / (4096 d^2) >= 4.6e-8 for
+    d <= 576; a nonzero numerator sum is at least 1, a mean of 1 / (64 d)), so for
+    those the rules only ever apply to windows that are exactly flat or exactly
+    zero-mean: the index itself.
   * The reconstruction is real-valued (no rounding or clipping), as for PSNR.
   * APE(m) = 100 |m_T - m_DCT| / |m_DCT|, on the averages over images.
 """
@@ -137,7 +142,7 @@ def sdct_numerators(img: np.ndarray, r: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 WIN = 8
-FLAT_EPS = 2.0 ** -24
+FLAT_EPS = 2.0 ** -32
 
 
 def uqi_map(x: np.ndarray, y: np.ndarray, win: int = WIN) -> np.ndarray:
@@ -192,8 +197,9 @@ def uqi_map_exact(x: np.ndarray, y_num: np.ndarray, d: int, win: int = WIN) -> n
     sy, syy, sxy = wsum(yn), wsum(yn * yn), wsum(x * yn)
     vx = n * sxx - sx * sx
     vy = n * syy - sy * sy                    # n^2 d^2 var_y
-    # The flat-window rules on exact integers (the bounds n^2 d^2 2^-24 and
-    # n d 2^-24 are exact in float64).
+    # The flat-window rules on exact integers (the bounds n^2 d^2 2^-32 and
+    # n d 2^-32 are exact in float64; below the integers' resolution, so they
+    # hold only for exactly flat or exactly zero-mean windows).
     flat_y = vy.astype(np.float64) <= n * n * d * d * FLAT_EPS
     vy = np.where(flat_y, 0, vy)
     cov = np.where((vx == 0) | flat_y, 0, n * sxy - sx * sy)

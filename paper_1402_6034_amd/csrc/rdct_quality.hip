@@ -127,14 +127,14 @@ __device__ __forceinline__ WinX window_x(double sx, double sxx, double d) {
 // its denominator is 0.  Float64 noise must not decide the index: a constant
 // block keeps only its DC term and is exact in real arithmetic, but the float64
 // transforms leave ~1e-13 of noise in it.  So, in grey levels, a
-// reconstruction window with variance <= 2^-24 counts as flat (no variance, no
-// covariance), a window mean of magnitude <= 2^-24 counts as 0, and a flat
+// reconstruction window with variance <= 2^-32 counts as flat (no variance, no
+// covariance), a window mean of magnitude <= 2^-32 counts as 0, and a flat
 // pixel window has no covariance.  With integer numerators every quantity here
 // is an exact integer and the rules are decided exactly.  The two factors
 // share one division.
 __device__ __forceinline__ double window_uqi(const WinX& w, double sx, double sy, double syy,
                                              double sxy, double d) {
-  constexpr double N = 64.0, EPS = 0x1p-24;
+  constexpr double N = 64.0, EPS = 0x1p-32;
   const double vy_raw = __builtin_fma(N, syy, -sy * sy);              // N^2 D^2 var_y
   const bool flat_y = vy_raw <= (N * N) * (d * d) * EPS;
   const double vy = flat_y ? 0.0 : vy_raw;
@@ -225,7 +225,7 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
     }
   }
   // Thresholds of the flat and zero-mean rules in numerator units.
-  const double flat_lim = (64.0 * 64.0) * (D * D) * 0x1p-24, mean_lim = 64.0 * D * 0x1p-24;
+  const double flat_lim = (64.0 * 64.0) * (D * D) * 0x1p-32, mean_lim = 64.0 * D * 0x1p-32;
   // Row task: pixel row hr, window columns 8 hs .. 8 hs + 7.
   const int hr = t % kPixRows, hs = t / kPixRows;
   // Owned pixels for the SSE: row t / 8, columns 4 (t % 8) .. + 3 of the tile.

@@ -258,3 +258,21 @@ def test_metrics_improve_with_r_and_dct_beats_approximations_on_mse():
         assert res["dct"]["mse"][r] <= res["rdct"]["mse"][r] + 1e-9
     # r = 1 keeps DC only; DCT and C_orth share the DC row (Section 2).
     assert res["dct"]["mse"][1] == pytest.approx(res["rdct"]["mse"][1], rel=1e-12)
+
+
+def test_exact_rule_resolves_one_numerator_unit():
+    # A flat pixel window against a reconstruction whose numerators differ by
+    # one unit in one pixel: Wang-Bovik's index has s_x^2 = 0 < s_y^2 and
+    # s_xy = 0, so f_s = 0 and Q = 0; the flat-window rule must not fire on
+    # exact integer data.  Checked by plain rational arithmetic with no rule.
+    from fractions import Fraction
+    x = np.full((8, 8), 100, dtype=np.int64)
+    for d in (576, 64):
+        y_num = d * x
+        y_num[3, 5] += 1
+        assert O.uqi_map_exact(x, y_num, d)[0, 0] == 0.0
+        ys = [Fraction(int(v), d) for v in y_num.ravel()]
+        my = sum(ys) / 64
+        vy = sum((v - my) ** 2 for v in ys) / 63
+        assert vy > 0                      # not flat: f_s = 2 * 0 / (0 + vy) = 0
+        assert O.uqi_window_exact(x, np.array(ys, dtype=object)) == 0
