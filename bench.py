@@ -124,11 +124,16 @@ def traffic_record(workload):
     if rec.get("source_sha256") != kernel_source_hash(workload):
         return None
     try:
-        return {"bytes": int(rec["traffic_bytes_per_launch"]),
-                "read": int(rec["read_bytes_per_launch"]),
-                "write": int(rec["write_bytes_per_launch"])}
+        out = {"bytes": int(rec["traffic_bytes_per_launch"]),
+               "read": int(rec["read_bytes_per_launch"]),
+               "write": int(rec["write_bytes_per_launch"])}
     except (KeyError, ValueError):
         return None
+    try:
+        out["profiler_us"] = float(rec["profiler_kernel_average_us"])
+    except (KeyError, ValueError):
+        pass
+    return out
 
 
 def log(msg):
@@ -1139,6 +1144,14 @@ def main():
     if tr:
         roofline["traffic_read"] = tr["read"]
         roofline["traffic_write"] = tr["write"]
+        if "profiler_us" in tr and "bytes_per_launch" in roofline:
+            # The dominant kernel alone as rocprofv3 timed it in the committed
+            # profile (the HIP-event figure above times a whole plan run, which
+            # for the strided batch layout includes the small clearing launch).
+            p_ms = tr["profiler_us"] * 1e-3
+            roofline["profiler_kernel_ms"] = round(p_ms, 5)
+            roofline["profiler_frac"] = round(
+                roofline["bytes_per_launch"] / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     valu = valu_record(wl.workload_key)
     if valu:
         # Issue rate of vector instructions against the chip's: every CU issues at
