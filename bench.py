@@ -74,11 +74,19 @@ def _code_only(text):
 
 
 def kernel_source_hash(workload):
+    """sha256 over the code (comments and blank lines removed) of the files that
+    decide the workload's dominant kernel and its launch, and over the compiler
+    flags of the build (its HIP_FLAGS list, not the rest of the build script)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES[workload] + _COMMON:
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             text = f.read()
-        h.update((text if rel.endswith(".py") else _code_only(text)).encode())
+        if rel.endswith(".py"):
+            text = text[text.index("HIP_FLAGS = ["):]
+            text = text[:text.index("]") + 1]
+        else:
+            text = _code_only(text)
+        h.update(text.encode())
     return h.hexdigest()
 
 
@@ -288,13 +296,14 @@ class InverseFrame:
 
 
 class SumsPipe:
-    """Read-back of a plan's error sums for steps run two deep.  submit(slot)
-    copies the sums into device buffer `slot` on the launch stream (a small
-    device-to-device copy), then a side stream copies that buffer into pinned
-    host buffer `slot`, so the transfer to the host overlaps the next step's
-    kernel; take(slot) waits for that transfer and returns the values.  (A copy
-    to the host behind the kernel on the launch stream measured 86 to 335 us per
-    step on the 256-plane sweep, against 97 us this way.)"""
+    """Read-back of a step's results (the PSNR values formed on the device) for
+    steps run two deep.  submit(slot) copies them into device buffer `slot` on
+    the launch stream (a small device-to-device copy), then a side stream copies
+    that buffer into pinned host buffer `slot`, so the transfer to the host
+    overlaps the next step's kernel; take(slot) waits for that transfer and
+    returns the values.  (A copy to the host behind the kernel on the launch
+    stream measured 86 to 335 us per step on the 256-plane sweep, against 97 us
+    this way.)"""
 
     def __init__(self, dev):
         import torch
@@ -375,18 +384,26 @@ class RetentionSweep:
     kernel_launch = launch
 
     def submit(self, slot):
-        """Enqueue one step: the plan run and the copy of its sums."""
+        """Enqueue one step: the plan run, the PSNR of its sums on the device
+        (per plane and r, and the average over planes at every r) and the copy
+        of those decibels to the host."""
+        import torch
         if getattr(self, "pipe", None) is None:
-            self.pipe = SumsPipe(self.plan.sse)
+            self.pixels = torch.full((self.n,), self.size * self.size, dtype=torch.int64,
+                                     device="cuda")
+            self.db = torch.empty(self.n * 45 + 45, dtype=torch.float64, device="cuda")
+            self.pipe = SumsPipe(self.db)
         self.plan.run()
+        self.R.rdct_psnr_device(self.plan.sse, 45, self.R.SEL_ZIGZAG, self.pixels,
+                                self.db[:self.n * 45], self.db[self.n * 45:])
         self.pipe.submit(slot)
 
     def finish(self, slot):
-        """Wait for the step in `slot` and turn its sums into per-plane PSNR and
-        the average PSNR over the planes for every r (Section 3's curve)."""
-        sse = self.pipe.take(slot)
-        self.psnr, self.avg_psnr = self.R.rdct_psnr_planes(
-            sse, 45, self.R.SEL_ZIGZAG, [self.size] * self.n, [self.size] * self.n, mean=True)
+        """Wait for the step in `slot`: per-plane PSNR and the average PSNR over
+        the planes for every r (Section 3's curve)."""
+        db = self.pipe.take(slot)
+        self.psnr = db[:self.n * 45].reshape(self.n, 45)
+        self.avg_psnr = db[self.n * 45:]
 
     def report(self):
         """Average PSNR over the planes at r = 1..45 (the paper's Fig. 3 measure,
@@ -659,20 +676,21 @@ class RaggedBatch:
     kernel_launch = launch
 
     def submit(self, slot):
-        """Enqueue one step: the plan run and the copy of its sums."""
+        """Enqueue one step: the plan run, the per-plane PSNR of its sums on the
+        device and the copy of those decibels to the host."""
+        import torch
         if getattr(self, "pipe", None) is None:
-            self.pipe = SumsPipe(self.plan.sse)
+            self.pixels = torch.tensor([it.width * it.height for it in self.items],
+                                       dtype=torch.int64, device="cuda")
+            self.db = torch.empty(len(self.items), dtype=torch.float64, device="cuda")
+            self.pipe = SumsPipe(self.db)
         self.plan.run()
+        self.R.rdct_psnr_device(self.plan.sse, 1, self.R.SEL_QUANT, self.pixels, self.db)
         self.pipe.submit(slot)
 
     def finish(self, slot):
-        """Wait for the step in `slot` and turn its sums into per-plane PSNR."""
-        import numpy as np
-        sse = self.pipe.take(slot)
-        if getattr(self, "widths", None) is None:
-            self.widths = np.array([it.width for it in self.items], dtype=np.int32)
-            self.heights = np.array([it.height for it in self.items], dtype=np.int32)
-        self.psnr = self.R.rdct_psnr_planes(sse, 1, self.R.SEL_QUANT, self.widths, self.heights)
+        """Wait for the step in `slot`: per-plane PSNR."""
+        self.psnr = self.pipe.take(slot)
 
     def step(self):
         self.submit(0)

@@ -161,6 +161,21 @@ rdct_status_t rdct_psnr_planes(const uint64_t* sse, int32_t n, int32_t r_count, 
                                const int32_t* widths, const int32_t* heights, double* psnr_out,
                                double* mean_out);
 
+/*
+ * rdct_psnr_planes on the device, asynchronous on `stream`: the decibels are
+ * formed where the sums are, so a caller that reads results back copies them
+ * and does no per-value arithmetic on the host.  DEVICE arrays:
+ *   sse       n * r_count raw sums (layout of rdct_psnr_planes);
+ *   pixels    n plane sizes in pixels (width * height);
+ *   psnr_out  n * r_count values, +inf for an exact reconstruction;
+ *   mean_out  optional: r_count means over the n planes (NaN when n = 0).
+ * No allocation.  Errors: INVALID_ARG (null or misaligned arrays, n < 0,
+ * r_count < 1, bad mode), UNSUPPORTED (more than 2^31 values), HIP.
+ */
+rdct_status_t rdct_psnr_device(const uint64_t* sse, int32_t n, int32_t r_count, int32_t mode,
+                               const int64_t* pixels, double* psnr_out, double* mean_out,
+                               void* stream);
+
 /* Number of 8x8 blocks of a plane: ceil(h/8) * ceil(w/8). */
 int64_t rdct_num_blocks(int32_t width, int32_t height);
 

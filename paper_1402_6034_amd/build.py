@@ -20,6 +20,7 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["rdct_kernels.hip", "rdct_quality.hip", "rdct_codec.hip", "rdct_stream.hip",
+           "rdct_psnr.hip",
            "rdct_api.cpp", "rdct_batch.cpp", "rdct_server.cpp", "rdct_tune.cpp",
            "rdct_transforms.cpp", "rdct_quality_api.cpp", "rdct_codec_api.cpp",
            "rdct_metrics.cpp"]

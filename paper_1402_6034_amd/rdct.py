@@ -148,6 +148,8 @@ def _declare_extra(L):
     L.rdct_quality_metrics.restype = c_int32
     L.rdct_psnr_planes.argtypes = [P, c_int32, c_int32, c_int32, P, P, P, P]
     L.rdct_psnr_planes.restype = c_int32
+    L.rdct_psnr_device.argtypes = [P, c_int32, c_int32, c_int32, P, P, P, P]
+    L.rdct_psnr_device.restype = c_int32
     L.rdct_codec_unpack_pairs.argtypes = [P, c_int64, P, P]
     L.rdct_codec_unpack_pairs.restype = c_int32
     L.rdct_stream_unit_bytes.argtypes = [c_int32, POINTER(c_int64), POINTER(c_int64)]
@@ -480,6 +482,18 @@ def rdct_psnr_planes(sse_raw, r_count, mode, widths, heights, mean=False):
            "rdct_psnr_planes")
     out = out.reshape(n, r_count)
     return (out, avg) if mean else out
+
+
+def rdct_psnr_device(sse, r_count, mode, pixels, psnr_out, mean_out=None, stream=None):
+    """PSNR of n planes on the device: sse (n * r_count int64/uint64 tensor),
+    pixels (n int64 tensor of width * height), psnr_out (n * r_count float64
+    tensor), optional mean_out (r_count float64 tensor); all on the device."""
+    n = pixels.numel()
+    if sse.numel() != n * r_count or psnr_out.numel() != n * r_count or \
+            (mean_out is not None and mean_out.numel() != r_count):
+        raise ValueError("sizes do not match")
+    _check(lib().rdct_psnr_device(_ptr(sse), n, r_count, mode, _ptr(pixels), _ptr(psnr_out),
+                                  _ptr(mean_out), _stream(stream)), "rdct_psnr_device")
 
 
 def rdct_codec_unpack_pairs(words):

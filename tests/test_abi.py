@@ -246,3 +246,13 @@ def test_pair_words_decode():
 def test_set_tuning_rejects_a_null_plan_and_invalid_geometry():
     t = R.Tuning(1, 4, 0, R.LAYOUT_STRIDED, 0)
     assert R.lib().rdct_batch_plan_set_tuning(None, ctypes.byref(t)) == R.ERR_INVALID_ARG
+
+
+@needs_no_gpu
+def test_device_psnr_rejects_bad_arguments():
+    L = R.lib()
+    assert L.rdct_psnr_device(None, 3, 1, R.SEL_ZIGZAG, None, None, None, None) == R.ERR_INVALID_ARG
+    assert L.rdct_psnr_device(1 << 20, 3, 0, R.SEL_ZIGZAG, 1 << 21, 1 << 22, None, None) == R.ERR_INVALID_ARG
+    assert L.rdct_psnr_device(1 << 20, 3, 1, 7, 1 << 21, 1 << 22, None, None) == R.ERR_INVALID_ARG
+    assert L.rdct_psnr_device(1 << 20 | 4, 3, 1, R.SEL_ZIGZAG, 1 << 21, 1 << 22, None,
+                              None) == R.ERR_INVALID_ARG

@@ -291,3 +291,30 @@ def test_sweep_is_monotone_and_shift_invariant():
     a, _, _ = R.compress_eval(g(shifted), R.select(R.SEL_ZIGZAG, r=1), 45)
     b, _, _ = R.compress_eval(g(half), R.select(R.SEL_ZIGZAG, r=1), 45)
     assert np.array_equal(host(a), host(b))
+
+
+def test_psnr_on_the_device_equals_the_host_call():
+    # rdct_psnr_device forms the same decibels as rdct_psnr_planes (and the mean
+    # over planes at every r), +inf for a zero sum, up to the last bits of the
+    # two log10 implementations.
+    rng = np.random.default_rng(21)
+    n, rc = 37, 9
+    widths = rng.integers(8, 600, n)
+    heights = rng.integers(8, 600, n)
+    sse = rng.integers(0, 2 ** 45, size=(n, rc)).astype(np.int64)
+    sse[3, 4] = 0
+    for mode in (R.SEL_ZIGZAG, R.SEL_QUANT):
+        want, want_mean = R.rdct_psnr_planes(sse, rc, mode, widths, heights, mean=True)
+        d_sse = torch.from_numpy(sse).to(DEV)
+        pix = torch.from_numpy((widths * heights).astype(np.int64)).to(DEV)
+        out = torch.empty(n * rc, dtype=torch.float64, device=DEV)
+        mean = torch.empty(rc, dtype=torch.float64, device=DEV)
+        R.rdct_psnr_device(d_sse, rc, mode, pix, out, mean)
+        got = host(out).reshape(n, rc)
+        assert np.isinf(got[3, 4]) and np.isinf(host(mean)[4])
+        fin = np.isfinite(want)
+        assert np.array_equal(fin, np.isfinite(got))
+        assert np.max(np.abs(got[fin] - want[fin])) < 1e-11
+        m = host(mean)
+        ok = np.isfinite(want_mean)
+        assert np.max(np.abs(m[ok] - want_mean[ok])) < 1e-11
