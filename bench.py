@@ -115,11 +115,21 @@ def valu_record(workload):
         return None
 
 
-def traffic_record(workload):
+def geometry_tag(cfg):
+    """Launch geometry of a batch plan as written in its profile records, from
+    the plan's config(); None for workloads without one."""
+    if "layout" not in cfg:
+        return None
+    return (f"{cfg['layout']} {cfg['waves_per_wg']} waves/WG x {cfg['wgs_per_cu']} WGs/CU "
+            f"xcd_ranges {int(cfg['xcd_ranges'])}")
+
+
+def traffic_record(workload, geometry=None):
     """HBM bytes per launch of the workload's dominant kernel, from the counter
     record profiles/<workload>_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled by
-    a device copy of known size).  None when there is no record or it was
-    taken on other kernel sources."""
+    a device copy of known size).  None when there is no record, it was taken
+    on other kernel sources, or (batch plans) at another launch geometry: the
+    order in which work items meet the L2s changes the bytes read."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -130,6 +140,8 @@ def traffic_record(workload):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
     if rec.get("source_sha256") != kernel_source_hash(workload):
+        return None
+    if geometry is not None and rec.get("geometry") != geometry:
         return None
     try:
         out = {"bytes": int(rec["traffic_bytes_per_launch"]),
@@ -295,42 +307,43 @@ class InverseFrame:
                           "float64 inverse"}
 
 
-class SumsPipe:
+class ResultPipe:
     """Read-back of a step's results (the PSNR values formed on the device) for
-    steps run two deep.  submit(slot) copies them into device buffer `slot` on
-    the launch stream (a small device-to-device copy), then a side stream copies
-    that buffer into pinned host buffer `slot`, so the transfer to the host
-    overlaps the next step's kernel; take(slot) waits for that transfer and
-    returns the values.  (A copy to the host behind the kernel on the launch
-    stream measured 86 to 335 us per step on the 256-plane sweep, against 97 us
-    this way.)"""
+    steps run two deep.  Step k writes its results into device buffer k & 1
+    (buffer(slot) first makes the launch stream wait until that buffer's last
+    transfer is done); submit(slot) has a side stream copy it into pinned host
+    buffer `slot`, so the transfer overlaps the next step's kernels; take(slot)
+    waits for that transfer and returns the values.  (A copy to the host behind
+    the kernel on the launch stream measured 86 to 335 us per step on the
+    256-plane sweep, against 97 us on a side stream.)"""
 
-    def __init__(self, dev):
+    def __init__(self, n, dtype):
         import torch
-        self.dev = dev
-        self.stage = [torch.empty_like(dev) for _ in range(2)]
-        self.bufs = [torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True) for _ in range(2)]
+        self.dev = [torch.empty(n, dtype=dtype, device="cuda") for _ in range(2)]
+        self.host = [torch.empty(n, dtype=dtype, pin_memory=True) for _ in range(2)]
         self.side = torch.cuda.Stream()
-        self.staged = [torch.cuda.Event() for _ in range(2)]
+        self.ready = [torch.cuda.Event() for _ in range(2)]
         self.copied = [torch.cuda.Event() for _ in range(2)]
         self.used = [False, False]
 
+    def buffer(self, slot):
+        import torch
+        if self.used[slot]:
+            torch.cuda.current_stream().wait_event(self.copied[slot])
+        return self.dev[slot]
+
     def submit(self, slot):
         import torch
-        main = torch.cuda.current_stream()
-        if self.used[slot]:
-            main.wait_event(self.copied[slot])     # the buffer's last transfer is done
-        self.stage[slot].copy_(self.dev)
-        self.staged[slot].record(main)
-        self.side.wait_event(self.staged[slot])
+        self.ready[slot].record(torch.cuda.current_stream())
+        self.side.wait_event(self.ready[slot])
         with torch.cuda.stream(self.side):
-            self.bufs[slot].copy_(self.stage[slot], non_blocking=True)
+            self.host[slot].copy_(self.dev[slot], non_blocking=True)
             self.copied[slot].record(self.side)
         self.used[slot] = True
 
     def take(self, slot):
         self.copied[slot].synchronize()
-        return self.bufs[slot].numpy()
+        return self.host[slot].numpy()
 
 
 def seeded_planes(n, size, planes_cache=None):
@@ -391,11 +404,12 @@ class RetentionSweep:
         if getattr(self, "pipe", None) is None:
             self.pixels = torch.full((self.n,), self.size * self.size, dtype=torch.int64,
                                      device="cuda")
-            self.db = torch.empty(self.n * 45 + 45, dtype=torch.float64, device="cuda")
-            self.pipe = SumsPipe(self.db)
+            self.pipe = ResultPipe(self.n * 45 + 45, torch.float64)
+            self.views = [(d[:self.n * 45], d[self.n * 45:]) for d in self.pipe.dev]
+        self.pipe.buffer(slot)
         self.plan.run()
-        self.R.rdct_psnr_device(self.plan.sse, 45, self.R.SEL_ZIGZAG, self.pixels,
-                                self.db[:self.n * 45], self.db[self.n * 45:])
+        db, mean = self.views[slot]
+        self.R.rdct_psnr_device(self.plan.sse, 45, self.R.SEL_ZIGZAG, self.pixels, db, mean)
         self.pipe.submit(slot)
 
     def finish(self, slot):
@@ -664,7 +678,7 @@ class RaggedBatch:
         self.nb = self.plan.n_blocks
         log(f"[bench] plan: {self.nb} blocks in {self.plan.n_items} work items")
         if autotune:
-            t = self.plan.autotune(reps=3)
+            t = self.plan.autotune(reps=10)
             log(f"[bench] tuned geometry: {LAYOUT_NAME[t.layout]}, {t.waves_per_wg} waves/WG x "
                 f"{t.wgs_per_cu} WGs/CU, XCD ranges {t.xcd_ranges}")
         self.px = sum(it.height * it.width for it in self.items)
@@ -682,10 +696,10 @@ class RaggedBatch:
         if getattr(self, "pipe", None) is None:
             self.pixels = torch.tensor([it.width * it.height for it in self.items],
                                        dtype=torch.int64, device="cuda")
-            self.db = torch.empty(len(self.items), dtype=torch.float64, device="cuda")
-            self.pipe = SumsPipe(self.db)
+            self.pipe = ResultPipe(len(self.items), torch.float64)
+        db = self.pipe.buffer(slot)
         self.plan.run()
-        self.R.rdct_psnr_device(self.plan.sse, 1, self.R.SEL_QUANT, self.pixels, self.db)
+        self.R.rdct_psnr_device(self.plan.sse, 1, self.R.SEL_QUANT, self.pixels, db)
         self.pipe.submit(slot)
 
     def finish(self, slot):
@@ -708,9 +722,10 @@ class RaggedBatch:
                 "graph": bool(t.use_graph)}
 
     def tuning_table(self, reps=10):
-        """Every geometry the autotuner considers, plus hipGraph replay of each,
-        timed on this plan (HIP events over `reps` back-to-back runs, median of
-        three rounds); the plan keeps its tuned geometry afterwards."""
+        """Every geometry the autotuner considers, the strided ones also in the
+        hardware's workgroup order, plus hipGraph replay of each, timed on this
+        plan (HIP events over `reps` back-to-back runs, median of three rounds);
+        the plan keeps its tuned geometry afterwards."""
         R = self.R
         keep = self.plan.tuning
         cands = []
@@ -1141,7 +1156,7 @@ def main():
     # Dominant kernel: average launch duration from HIP events.
     reps = max(20, args.steps)
     k_ms = event_time_ms(lambda i: wl.kernel_launch(i), reps)
-    tr = traffic_record(wl.workload_key)
+    tr = traffic_record(wl.workload_key, geometry_tag(wl.config()))
     if getattr(wl, "roofline_kind", "hbm") == "alu":
         flops = wl.flops_per_launch
         achieved = flops / (k_ms * 1e-3) / 1e12

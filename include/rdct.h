@@ -217,7 +217,8 @@ typedef struct {
   int32_t xcd_ranges;      /* STRIDED: 1 = workgroups remapped so that each of the
                               eight XCDs (each with its own L2) takes a contiguous
                               range of work items, so neighbouring items share an
-                              L2; 0 = the hardware's round-robin order              */
+                              L2 (the default, and the order the autotuner times);
+                              0 = the hardware's round-robin order                  */
 } rdct_tuning_t;
 
 typedef struct rdct_batch_plan rdct_batch_plan_t;
@@ -277,10 +278,12 @@ rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tun
 rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
                                    int32_t* n_items, rdct_tuning_t* used);
 
-/* Time every candidate geometry on this plan (both layouts; three rounds of reps
-   back-to-back launches each, timed with HIP events, the median round's average;
-   synchronous), adopt the fastest, store it in
-   the tuning cache (file named by RDCT_TUNING_CACHE, default
+/* Time every candidate geometry on this plan (both layouts; five rounds that
+   each queue reps launches of every candidate in turn, back to back, timed with
+   HIP events between candidates; a candidate's median round is its time;
+   synchronous), adopt, among the candidates within 2% of the fastest, the one
+   with the fewest resident waves per CU (then the faster),
+   store it in the tuning cache (file named by RDCT_TUNING_CACHE, default
    ~/.cache/rdct_tuning.json, keyed by architecture, path variant, size class
    and plane-count class) and return it in *best. */
 rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* stream,

@@ -288,7 +288,10 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   // the host on the same stream stalled (537 against 81 us per run and copy).
   t.use_graph = 0;
   t.layout = RDCT_LAYOUT_STRIDED;
-  t.xcd_ranges = 0;
+  // Each XCD takes a contiguous range of items: neighbouring items share an L2,
+  // so boundary lines are read once (the ragged batch reads 1.05x its planes
+  // this way against 1.18x in the hardware's order, at the same or better speed).
+  t.xcd_ranges = 1;
   rdct_tuning_t cached;
   if (tune_cache_lookup(p->key, &cached)) {
     rdct_tuning_t c = t;
@@ -388,22 +391,20 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
                                   rdct_tuning_t* best) {
   if (!plan || reps < 1 || reps > 1000) return RDCT_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RDCT_ERR_HIP;
-  // Candidates: the strided layout over waves per workgroup x resident waves
-  // per CU x XCD ranges, and the per-plane layout over waves per workgroup.
+  // Candidates: the strided layout (in the XCD-range order, which reads fewer
+  // bytes and measured as fast or faster at every geometry from 4 resident
+  // waves per CU up) over waves per workgroup x resident waves per CU, and the
+  // per-plane layout over waves per workgroup.
   std::vector<rdct_tuning_t> cands;
   for (int wpg : {1, 2, 4}) {
     for (int waves : {2, 4, 8, 12, 16}) {
       if (waves % wpg) continue;
-      for (int xcd : {0, 1}) {
-        rdct_tuning_t t = plan->tuning;
-        t.layout = RDCT_LAYOUT_STRIDED;
-        t.waves_per_wg = wpg;
-        t.wgs_per_cu = waves / wpg;
-        t.xcd_ranges = xcd;
-        cands.push_back(t);
-      }
+      rdct_tuning_t t = plan->tuning;
+      t.layout = RDCT_LAYOUT_STRIDED;
+      t.waves_per_wg = wpg;
+      t.wgs_per_cu = waves / wpg;
+      t.xcd_ranges = 1;
+      cands.push_back(t);
     }
     rdct_tuning_t t = plan->tuning;
     t.layout = RDCT_LAYOUT_PER_PLANE;
@@ -412,42 +413,70 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
     t.xcd_ranges = 0;
     cands.push_back(t);
   }
-  float best_us = 1e30f;
-  rdct_tuning_t best_t = plan->tuning;
+  cands.erase(std::remove_if(cands.begin(), cands.end(),
+                             [](const rdct_tuning_t& t) { return !valid_tuning(t); }),
+              cands.end());
+  // Each candidate gets one untimed launch, then kRounds rounds; a round
+  // queues `reps` launches of every candidate in turn, back to back with no
+  // synchronisation in between (as runs follow each other in use), an event
+  // before and after each candidate's launches, and waits once at its end.  A
+  // drift of the clock or temperature during the search thus weighs on every
+  // candidate alike, the GPU never idles between candidates, and a candidate's
+  // median round decides.  Timing single launches between synchronisations
+  // ranked the ragged batch's geometries differently from back-to-back runs
+  // (1.35 against 1.31 ms for the pick), and so did short rounds that each
+  // began after a synchronisation.
+  constexpr int kRounds = 5;
+  const size_t nc = cands.size();
+  std::vector<hipEvent_t> ev(nc + 1, nullptr);
+  std::vector<std::vector<float>> us(nc);
   rdct_status_t st = RDCT_OK;
-  for (const rdct_tuning_t& t : cands) {
-    if (!valid_tuning(t)) continue;
-    // One untimed launch, then three rounds of `reps` launches back to back (as
-    // runs follow each other in use), each round timed as a whole.  Timing single
-    // launches between synchronisations ranked the ragged batch's geometries
-    // differently from back-to-back runs (1.35 against 1.31 ms for the pick).
-    if (launch_direct(plan, t, s) != hipSuccess) {
-      st = RDCT_ERR_HIP;
-      break;
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = RDCT_ERR_HIP;
+  for (size_t c = 0; c < nc && st == RDCT_OK; ++c)
+    if (launch_direct(plan, cands[c], s) != hipSuccess) st = RDCT_ERR_HIP;
+  for (int round = 0; round < kRounds && st == RDCT_OK; ++round) {
+    bool ok = hipEventRecord(ev[0], s) == hipSuccess;
+    for (size_t c = 0; c < nc && ok; ++c) {
+      for (int r = 0; r < reps && ok; ++r) ok = launch_direct(plan, cands[c], s) == hipSuccess;
+      ok = ok && hipEventRecord(ev[c + 1], s) == hipSuccess;
     }
-    std::vector<float> us;
-    for (int round = 0; round < 3 && st == RDCT_OK; ++round) {
-      bool ok = hipEventRecord(e0, s) == hipSuccess;
-      for (int r = 0; r < reps && ok; ++r) ok = launch_direct(plan, t, s) == hipSuccess;
-      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    ok = ok && hipEventSynchronize(ev[nc]) == hipSuccess;
+    for (size_t c = 0; c < nc && ok; ++c) {
       float ms = 0.f;
-      if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = RDCT_ERR_HIP;
-        break;
-      }
-      us.push_back(ms * 1000.f / reps);
+      ok = hipEventElapsedTime(&ms, ev[c], ev[c + 1]) == hipSuccess;
+      us[c].push_back(ms * 1000.f / reps);
     }
-    if (st != RDCT_OK) break;
-    std::sort(us.begin(), us.end());
-    const float med = us[us.size() / 2];
-    if (med < best_us) {
-      best_us = med;
-      best_t = t;
+    if (!ok) st = RDCT_ERR_HIP;
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st != RDCT_OK) return st;
+  std::vector<float> med(nc);
+  float fastest = 1e30f;
+  for (size_t c = 0; c < nc; ++c) {
+    std::sort(us[c].begin(), us[c].end());
+    med[c] = us[c][us[c].size() / 2];
+    fastest = std::min(fastest, med[c]);
+  }
+  // Among the candidates within 2% of the fastest, the fewest resident waves
+  // per CU (then the faster).  On the ragged batch the geometries from 4 to 16
+  // resident waves land within 2-3% of each other in such short rounds, in an
+  // order that changes from run to run, while runs of hundreds of plans at a
+  // time measured 1 x 4 at 1.30-1.31 ms against 1.33-1.35 ms for 4 x 3 or
+  // 1 x 12.
+  float best_us = 1e30f;
+  int best_waves = 1 << 30;
+  rdct_tuning_t best_t = plan->tuning;
+  for (size_t c = 0; c < nc; ++c) {
+    if (med[c] > fastest * 1.02f) continue;
+    const int waves = cands[c].waves_per_wg * cands[c].wgs_per_cu;
+    if (waves < best_waves || (waves == best_waves && med[c] < best_us)) {
+      best_waves = waves;
+      best_us = med[c];
+      best_t = cands[c];
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != RDCT_OK) return st;
   plan->tuning = best_t;
   plan->graph_ready = false;  // re-captured on the next run
   tune_cache_store(plan->key, best_t, best_us);

@@ -48,6 +48,12 @@ struct TransformTables {
   double G[64];
   double D;
   int32_t exact;
+  // Integer copies of F, G and D, valid when int_form is 1: the tables are
+  // integral and small enough that the comparison kernel's integer form (int32
+  // numerators, 24-bit multiplies) stays in range for every r and 8-bit input.
+  int32_t Fi[64], Gi[64];
+  int32_t Di;
+  int32_t int_form;
 };
 rdct_status_t build_transform(int id, TransformTables* out);
 

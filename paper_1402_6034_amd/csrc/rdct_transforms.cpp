@@ -119,6 +119,41 @@ bool polar_orthogonal(const double c0[8][8], double t[8][8]) {
   return true;
 }
 
+// Integer form of exact tables.  With 8-bit pixels x, |Y_kl| <= 255 a_k a_l for
+// a_k = sum_m |F_km|, and any keep-r numerator is at most
+// sum_kl |Y_kl| |G_ik| |G_jl| <= 255 (max_i sum_k a_k |G_ik|)^2 = N.  The
+// integer kernel needs |Y| max|G| < 2^23 (24-bit multiply operands),
+// 8 N < 2^31 (8-pixel row sums of numerators) and 255 D + N < 2^31 (errors).
+void set_integer_form(TransformTables* t) {
+  t->int_form = 0;
+  if (!t->exact) return;
+  for (int i = 0; i < 64; ++i) {
+    if (t->F[i] != std::nearbyint(t->F[i]) || std::fabs(t->F[i]) > 127.0) return;
+    if (t->G[i] != std::nearbyint(t->G[i]) || std::fabs(t->G[i]) > 127.0) return;
+    t->Fi[i] = (int32_t)t->F[i];
+    t->Gi[i] = (int32_t)t->G[i];
+  }
+  if (t->D != std::nearbyint(t->D) || t->D < 1.0 || t->D > 4096.0) return;
+  t->Di = (int32_t)t->D;
+  double a[8], a_max = 0.0, g_max = 0.0, row_max = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    a[k] = 0.0;
+    for (int m = 0; m < 8; ++m) a[k] += std::fabs(t->F[k * 8 + m]);
+    a_max = std::fmax(a_max, a[k]);
+  }
+  for (int i = 0; i < 8; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) {
+      s += a[k] * std::fabs(t->G[i * 8 + k]);
+      g_max = std::fmax(g_max, std::fabs(t->G[i * 8 + k]));
+    }
+    row_max = std::fmax(row_max, s);
+  }
+  const double y_max = 255.0 * a_max * a_max, n_max = 255.0 * row_max * row_max;
+  if (y_max * g_max >= 0x1p23 || 8.0 * n_max >= 0x1p31 || 255.0 * t->D + n_max >= 0x1p31) return;
+  t->int_form = 1;
+}
+
 void set_orthogonal(const double t[8][8], TransformTables* out) {
   for (int k = 0; k < 8; ++k)
     for (int n = 0; n < 8; ++n) {
@@ -127,11 +162,13 @@ void set_orthogonal(const double t[8][8], TransformTables* out) {
     }
   out->D = 1.0;
   out->exact = 0;
+  out->int_form = 0;
 }
 
 }  // namespace
 
 rdct_status_t build_transform(int id, TransformTables* out) {
+  *out = TransformTables{};
   double c[8][8];
   dct_matrix(c);
   switch (id) {
@@ -148,6 +185,7 @@ rdct_status_t build_transform(int id, TransformTables* out) {
         }
       out->D = 576.0;
       out->exact = 1;
+      set_integer_form(out);
       return RDCT_OK;
     }
     case RDCT_T_SDCT: {
@@ -165,6 +203,7 @@ rdct_status_t build_transform(int id, TransformTables* out) {
         }
       out->D = 64.0;
       out->exact = 1;
+      set_integer_form(out);
       return RDCT_OK;
     }
     case RDCT_T_RDCT_CEIL:

@@ -318,3 +318,32 @@ def test_psnr_on_the_device_equals_the_host_call():
         m = host(mean)
         ok = np.isfinite(want_mean)
         assert np.max(np.abs(m[ok] - want_mean[ok])) < 1e-11
+
+
+@pytest.mark.parametrize("pattern", [R.STREAM_READ, R.STREAM_WRITE, R.STREAM_COPY, R.STREAM_R1W2,
+                                     R.STREAM_R1W6])
+@pytest.mark.parametrize("flags,wpc", [(0, 0), (3, 0), (2, 2), (7, 4)])
+def test_stream_calibration_moves_what_it_says(pattern, flags, wpc):
+    # The calibration kernel's stores: unit u's j-th KiB of output is the
+    # (j mod RL)-th KiB of its input with every 32-bit word XORed with j (for
+    # pure writes, the words (u, lane, 0, 0) XOR j); every unit is written once,
+    # whatever the load / store kinds, the grid and the XCD order.
+    rb, wb = R.rdct_stream_unit_bytes(pattern)
+    units = 37
+    src = torch.randint(0, 2 ** 31 - 1, (max(units * rb // 4, 4),), dtype=torch.int32, device=DEV)
+    dst = torch.full((max(units * wb // 4, 256),), -1, dtype=torch.int32, device=DEV)
+    R.rdct_stream(src if rb else None, dst, units, pattern, flags, wpc)
+    torch.cuda.synchronize()
+    if wb == 0:
+        return   # reads only: the destination is written for one value of the data only
+    rl, wl = rb // 1024, wb // 1024
+    d = host(dst).view(np.uint32).reshape(units, wl, 64, 4)
+    if rl:
+        sv = host(src).view(np.uint32).reshape(units, rl, 64, 4)
+        want = np.stack([sv[:, j % rl] ^ np.uint32(j) for j in range(wl)], axis=1)
+    else:
+        base = np.zeros((units, 64, 4), dtype=np.uint32)
+        base[:, :, 0] = np.arange(units, dtype=np.uint32)[:, None]
+        base[:, :, 1] = np.arange(64, dtype=np.uint32)[None, :]
+        want = np.stack([base ^ np.uint32(j) for j in range(wl)], axis=1)
+    assert np.array_equal(d, want)
