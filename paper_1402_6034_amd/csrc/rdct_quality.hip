@@ -472,6 +472,7 @@ __device__ void quality_tile_int(const QPlane& P, int tile, const RDCT_CONST Qua
   // x^2 (integers below 2^23).
   const int c = t & (kWinCols - 1), g = t / kWinCols;
   int sxw[kWinPerThread], sxxw[kWinPerThread];
+  double dvx[kWinPerThread], dsxx[kWinPerThread];   // D^2 N^2 var_x, D^2 sx^2
   bool w_ok[kWinPerThread], x_special[kWinPerThread];
   // D^2 x^2 over the thread's owned pixels if c is a multiple of 8: rows
   // 4 g .. 4 g + 3, columns c .. c + 7 (0 off the plane); these segments cover
@@ -502,6 +503,8 @@ __device__ void quality_tile_int(const QPlane& P, int tile, const RDCT_CONST Qua
       }
       sxw[m] = a;
       sxxw[m] = a2;
+      dvx[m] = D * D * (double)(__mul24(64, a2) - __mul24(a, a));
+      dsxx[m] = D * D * (double)a * (double)a;
       if (m == 0 && (c & 7) == 0)
         own_x2 = D * D * (double)(hxx[0] + hxx[1] + hxx[2] + hxx[3]);
       w_ok[m] = col_ok && (y0 + kWinPerThread * g + m + 8 <= P.height);
@@ -624,8 +627,9 @@ __device__ void quality_tile_int(const QPlane& P, int tile, const RDCT_CONST Qua
         w[3] = core + ((h8 + h9) + h10);
         return head + h3;
       };
-      // As for the pixels: the window terms of x are rebuilt from the integer
-      // sums each time rather than held in float64 across iterations.
+      // As for the pixels: the window sums of x are converted where they are
+      // used rather than held in float64 across iterations (the two terms
+      // that cost most to rebuild are held).
 #pragma unroll
       for (int m = 0; m < kWinPerThread; ++m) asm volatile("" : "+v"(sxw[m]), "+v"(sxxw[m]));
       int iy[kWinPerThread];
@@ -652,12 +656,10 @@ __device__ void quality_tile_int(const QPlane& P, int tile, const RDCT_CONST Qua
 #pragma unroll
         for (int m = 0; m < kWinPerThread; ++m) {
           const double sx = (double)sxw[m];
-          const double vx = (double)(__mul24(64, sxxw[m]) - __mul24(sxw[m], sxw[m]));
-          const double dd = D * D;
           const double vy = __builtin_fma(64.0, wyy[m], -wy[m] * wy[m]);
           const double cov = __builtin_fma(64.0, wxy[m], -sx * wy[m]);
-          den[m] = __builtin_fma(dd, vx, vy) * __builtin_fma(wy[m], wy[m], dd * sx * sx);
-          const double kq = w_ok[m] ? 4.0 * dd * sx : 0.0;
+          den[m] = (dvx[m] + vy) * __builtin_fma(wy[m], wy[m], dsxx[m]);
+          const double kq = w_ok[m] ? 4.0 * D * D * sx : 0.0;
           num[m] = kq * cov * wy[m];
         }
         q_acc = quotient_sum4(num, den);
