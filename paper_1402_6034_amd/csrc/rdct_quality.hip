@@ -163,12 +163,21 @@ __device__ __forceinline__ double window_uqi(const WinX& w, double sx, double sy
   return quotient(ns * nm, (zs ? 1.0 : ds) * (zm ? 1.0 : dm));
 }
 
+// Byte u of pixels packed four to a word.
+__device__ __forceinline__ int packed_pixel(const uint32_t* w, int u) {
+  return (int)((w[u >> 2] >> (8 * (u & 3))) & 0xffu);
+}
+
 __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST QualityArgs* A) {
   __shared__ double s_y[kPixRows][kYStride];
-  __shared__ float s_x[kPixRows][kYStride];
   __shared__ double s_h[3][kPixRows][kHStride];     // row sums of y, y^2, x y
   __shared__ double s_F[64], s_G[64];
   __shared__ double s_red[2][2][kThreads / 64];    // (UQI, SSE) x (r & 1) x wave
+  // The tile's pixels are staged only until every thread holds its own in
+  // registers; they share storage with the row sums, first written later.
+  static_assert(sizeof(s_h[1]) >= kPixRows * kPixCols, "pixel stage fits");
+  uint8_t* s_x8 = reinterpret_cast<uint8_t*>(&s_h[1][0][0]);
+  auto xat = [&](int row, int col) { return (double)s_x8[row * kPixCols + col]; };
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -184,9 +193,9 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
   for (int p = t; p < kPixRows * kPixCols; p += kThreads) {
     const int row = p / kPixCols, col = p - row * kPixCols;
     const int gy = y0 + row, gx = x0 + col;
-    float v = 0.0f;
-    if (gy < P.height && gx < P.width) v = (float)P.src[(int64_t)gy * P.pitch + gx];
-    s_x[row][col] = v;
+    uint8_t v = 0;
+    if (gy < P.height && gx < P.width) v = P.src[(int64_t)gy * P.pitch + gx];
+    s_x8[p] = v;
     s_y[row][col] = 0.0;
   }
   if (t < 64) s_F[t] = A->T.F[t];
@@ -201,7 +210,7 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
   const bool u_on = ub < kTileBlocks && by0 + ubr < nby && bx0 + ubc < nbx;
   double xcol[8];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) xcol[m] = u_on ? (double)s_x[ubr * 8 + m][ubc * 8 + ui] : 0.0;
+  for (int m = 0; m < 8; ++m) xcol[m] = u_on ? xat(ubr * 8 + m, ubc * 8 + ui) : 0.0;
 
   // This thread's windows: column c, rows 4 g .. 4 g + 3.  Their sums of x and
   // x^2 (exact integers) and the terms built from them.
@@ -220,7 +229,7 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
       double a = 0.0, a2 = 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double xv = (double)s_x[kWinPerThread * g + rr][c + u];
+        const double xv = xat(kWinPerThread * g + rr, c + u);
         a += xv;
         a2 = __builtin_fma(xv, xv, a2);
       }
@@ -246,9 +255,17 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
   }
   // Thresholds of the flat and zero-mean rules in numerator units.
   const double flat_lim = (64.0 * 64.0) * (D * D) * 0x1p-32, mean_lim = 64.0 * D * 0x1p-32;
-  // Row task: pixel row hr, window columns 8 hs .. 8 hs + 7.
+  // Row task: pixel row hr, window columns 8 hs .. 8 hs + 7; its 15 pixels
+  // (rows 0 .. 38 feed windows).
   const int hr = t % kPixRows, hs = t / kPixRows;
-  __syncthreads();
+  const bool row_task = t < kRowTasks && hr < kWinRows + 7;
+  uint32_t xr[4] = {0u, 0u, 0u, 0u};
+  if (row_task) {
+#pragma unroll
+    for (int u = 0; u < kSeg + 7; ++u)
+      xr[u >> 2] |= (uint32_t)xat(hr, kSeg * hs + u) << (8 * (u & 3));
+  }
+  __syncthreads();   // the pixel stage is reused from here on
 
   const int r_first = A->r_first, r_last = A->r_first + A->r_count - 1;
   // Add coefficient (k, l) of rank r - 1 of every block times its basis image
@@ -290,14 +307,16 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
     const bool scored = r >= r_first;
     if (scored) {
       // Row sums over 8 pixels, sliding along the row.
-      if (t < kRowTasks) {
+      if (row_task) {
+        // The empty asm keeps the pixels packed across iterations of r.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(xr[i]));
         const double* yr = &s_y[hr][kSeg * hs];
-        const float* xr = &s_x[hr][kSeg * hs];
         double yv[kSeg + 7], xv[kSeg + 7];
 #pragma unroll
         for (int u = 0; u < kSeg + 7; ++u) {
           yv[u] = yr[u];
-          xv[u] = (double)xr[u];
+          xv[u] = (double)packed_pixel(xr, u);
         }
         double a = 0.0, a2 = 0.0, ax = 0.0;
 #pragma unroll
@@ -416,10 +435,6 @@ __device__ __forceinline__ int block_sum8_i32(int v) {
   return v;
 }
 
-// Byte u of pixels packed four to a word.
-__device__ __forceinline__ int packed_pixel(const uint32_t* w, int u) {
-  return (int)((w[u >> 2] >> (8 * (u & 3))) & 0xffu);
-}
 
 __device__ void quality_tile_int(const QPlane& P, int tile, const RDCT_CONST QualityArgs* A) {
   __shared__ int32_t s_y[kPixRows][kYStride];        // reconstruction numerators
