@@ -56,11 +56,27 @@ def test_zigzag_codec(h, w, r):
 
 
 @pytest.mark.parametrize("h,w", SHAPES)
-@pytest.mark.parametrize("quality", [10, 50, 90])
+@pytest.mark.parametrize("quality", [1, 10, 50, 90, 100])
 def test_quant_codec(h, w, quality):
     img = synth.render_np(h + w + quality, h, w)
     enc = O.codec_encode(img, "quant", quality=quality, level_shift=128)
     c = run_codec(img, R.select(R.SEL_QUANT, quality=quality, level_shift=128))
+    check_pairs(c, enc)
+    got = c.recon.cpu().numpy()
+    a = enc["recon_float"]
+    near = np.abs(np.abs(a - np.floor(a)) - 0.5) < 1e-9
+    assert np.array_equal(got[~near], enc["recon_u8"][~near])
+
+
+def test_quant_codec_dense_groups():
+    """Uniform noise at quality 100: nearly every coefficient survives, so the
+    first 64-block group fills its slot almost to the 4096 pairs it holds, and
+    every wave takes the reconstruction's dense path (more than 10 nonzero
+    positions)."""
+    img = np.random.default_rng(5).integers(0, 256, size=(64, 136), dtype=np.uint8)
+    enc = O.codec_encode(img, "quant", quality=100, level_shift=128)
+    assert int(np.sum(enc["counts"][:64])) > 4000
+    c = run_codec(img, R.select(R.SEL_QUANT, quality=100, level_shift=128))
     check_pairs(c, enc)
     got = c.recon.cpu().numpy()
     a = enc["recon_float"]
