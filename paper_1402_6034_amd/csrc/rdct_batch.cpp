@@ -470,7 +470,13 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
   rdct_tuning_t best_t = plan->tuning;
   for (size_t c = 0; c < nc; ++c) {
     if (med[c] > fastest * 1.02f) continue;
-    const int waves = cands[c].waves_per_wg * cands[c].wgs_per_cu;
+    // Resident waves per CU: the strided grid holds wgs_per_cu workgroups per
+    // CU; the per-plane grid one workgroup per plane.
+    const int64_t cus = std::max(plan->n_cu, 1);
+    const int waves =
+        cands[c].layout == RDCT_LAYOUT_PER_PLANE
+            ? (int)std::min<int64_t>((plan->n_planes * cands[c].waves_per_wg + cus - 1) / cus, 1 << 20)
+            : cands[c].waves_per_wg * cands[c].wgs_per_cu;
     if (waves < best_waves || (waves == best_waves && med[c] < best_us)) {
       best_waves = waves;
       best_us = med[c];

@@ -419,8 +419,8 @@ __device__ void quality_tile(const QPlane& P, int tile, const RDCT_CONST Quality
 // above, but the reconstruction numerators and their 8-pixel row sums are
 // int32, each coefficient comes from 24-bit multiplies and 32-bit lane sums,
 // and only what leaves 32 bits (squares, products with x, errors) is float64:
-// every quantity is still exact.  After set-up the pixels live in registers,
-// so a workgroup holds about 33 KB of LDS instead of 52 KB and four
+// every quantity is still exact.  With 32-bit numerators and row sums a
+// workgroup holds about 33 KB of LDS (the float64 form 46 KB), so four
 // workgroups share a CU.
 // ---------------------------------------------------------------------------
 constexpr int kSumPixRows = kWinRows + 7;                    // 39 rows feed windows

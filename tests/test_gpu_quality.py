@@ -100,6 +100,23 @@ def test_flat_regions(t):
     check(img, t, 1, 45, host(sse), host(uqi))
 
 
+@pytest.mark.parametrize("t", [R.T_RDCT, R.T_SDCT, R.T_DCT])
+@pytest.mark.parametrize("pattern", ["checker", "stripes", "noise"])
+def test_extreme_contrast(t, pattern):
+    # Full-range patterns drive the reconstruction numerators and the window
+    # sums towards their largest magnitudes (the integer form's range).
+    h, w = 48, 72
+    yy, xx = np.mgrid[0:h, 0:w]
+    if pattern == "checker":
+        img = np.where((yy + xx) % 2 == 0, 255, 0).astype(np.uint8)
+    elif pattern == "stripes":
+        img = np.where((xx // 3 + yy // 5) % 2 == 0, 255, 0).astype(np.uint8)
+    else:
+        img = np.random.default_rng(11).choice(np.array([0, 255], dtype=np.uint8), size=(h, w))
+    sse, uqi = R.quality_sweep(g(img), t, 1, 64)
+    check(img, t, 1, 64, host(sse), host(uqi))
+
+
 def test_pitched_plane():
     img = synth.render_np(9, 64, 64)
     buf = torch.zeros((64, 80), dtype=torch.uint8, device=DEV)
