@@ -121,27 +121,32 @@ def geometry_tag(cfg):
     if "layout" not in cfg:
         return None
     return (f"{cfg['layout']} {cfg['waves_per_wg']} waves/WG x {cfg['wgs_per_cu']} WGs/CU "
-            f"xcd_ranges {int(cfg['xcd_ranges'])}")
+            f"xcd_ranges {int(cfg['xcd_ranges'])} strip {cfg.get('strip', 1)}")
 
 
 def traffic_record(workload, geometry=None):
     """HBM bytes per launch of the workload's dominant kernel, from the counter
-    record profiles/<workload>_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled by
-    a device copy of known size).  None when there is no record, it was taken
-    on other kernel sources, or (batch plans) at another launch geometry: the
-    order in which work items meet the L2s changes the bytes read."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    rec = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                rec[k.strip()] = v.strip()
-    if rec.get("source_sha256") != kernel_source_hash(workload):
-        return None
-    if geometry is not None and rec.get("geometry") != geometry:
+    records profiles/<workload>_traffic*.txt (FETCH_SIZE and WRITE_SIZE scaled
+    by a device copy of known size; batch plans keep one record per profiled
+    launch geometry, since the order in which work items meet the L2s changes
+    the bytes read).  None when no record was taken on the current kernel
+    sources (and, for batch plans, at the geometry the plan runs)."""
+    import glob
+    rec = None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{workload}_traffic*.txt"))):
+        r = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    r[k.strip()] = v.strip()
+        if r.get("source_sha256") != kernel_source_hash(workload):
+            continue
+        if geometry is not None and r.get("geometry") != geometry:
+            continue
+        rec = r
+        break
+    if rec is None:
         return None
     try:
         out = {"bytes": int(rec["traffic_bytes_per_launch"]),
@@ -387,7 +392,7 @@ class RetentionSweep:
         if autotune:
             t = self.plan.autotune(reps=5)
             log(f"[bench] autotuned: {LAYOUT_NAME[t.layout]}, waves/wg {t.waves_per_wg}, "
-                f"wg/cu {t.wgs_per_cu}")
+                f"wg/cu {t.wgs_per_cu}, strip {t.strip}")
         self.nb1 = (size // 8) ** 2
         self.psnr = None
 
@@ -440,7 +445,7 @@ class RetentionSweep:
                 "r": [1, 45], "coef": "int32", "layout": LAYOUT_NAME[t.layout],
                 "kernel_launches_per_step": 1 if t.layout == 2 else 2,
                 "waves_per_wg": t.waves_per_wg, "wgs_per_cu": t.wgs_per_cu,
-                "xcd_ranges": bool(t.xcd_ranges), "graph": bool(t.use_graph)}
+                "xcd_ranges": bool(t.xcd_ranges), "strip": t.strip, "graph": bool(t.use_graph)}
 
     def plain(self, steps=3):
         """The same sweep as one rdct_compress_eval launch per plane."""
@@ -680,7 +685,7 @@ class RaggedBatch:
         if autotune:
             t = self.plan.autotune(reps=10)
             log(f"[bench] tuned geometry: {LAYOUT_NAME[t.layout]}, {t.waves_per_wg} waves/WG x "
-                f"{t.wgs_per_cu} WGs/CU, XCD ranges {t.xcd_ranges}")
+                f"{t.wgs_per_cu} WGs/CU, XCD ranges {t.xcd_ranges}, strip {t.strip}")
         self.px = sum(it.height * it.width for it in self.items)
         self.psnr = None
 
@@ -718,30 +723,33 @@ class RaggedBatch:
         return {"workload": self.name, "planes": len(self.items), "blocks": self.nb,
                 "pixels": self.px, "coef": "int16", "recon": "float32", "level_shift": 128,
                 "layout": LAYOUT_NAME[t.layout], "waves_per_wg": t.waves_per_wg,
-                "wgs_per_cu": t.wgs_per_cu, "xcd_ranges": bool(t.xcd_ranges),
+                "wgs_per_cu": t.wgs_per_cu, "xcd_ranges": bool(t.xcd_ranges), "strip": t.strip,
                 "graph": bool(t.use_graph)}
 
     def tuning_table(self, reps=10):
-        """Every geometry the autotuner considers, the strided ones also in the
-        hardware's workgroup order, plus hipGraph replay of each, timed on this
-        plan (HIP events over `reps` back-to-back runs, median of three rounds);
-        the plan keeps its tuned geometry afterwards."""
+        """Every geometry the autotuner considers (the strided ones with strips of
+        1, 2, 4 and 8 items, and with one item also in the hardware's workgroup
+        order), plus hipGraph replay of each, timed on this plan (HIP events over
+        `reps` back-to-back runs, median of three rounds); the plan keeps its
+        tuned geometry afterwards."""
         R = self.R
         keep = self.plan.tuning
         cands = []
         for wpg in (1, 2, 4):
             for waves in (2, 4, 8, 12, 16):
                 if waves % wpg == 0:
-                    for xcd in (0, 1):
-                        cands.append((wpg, waves // wpg, R.LAYOUT_STRIDED, xcd))
-            cands.append((wpg, 1, R.LAYOUT_PER_PLANE, 0))
+                    cands.append((wpg, waves // wpg, R.LAYOUT_STRIDED, 0, 1))
+                    for strip in (1, 2, 4, 8):
+                        cands.append((wpg, waves // wpg, R.LAYOUT_STRIDED, 1, strip))
+            cands.append((wpg, 1, R.LAYOUT_PER_PLANE, 0, 1))
         rows = []
-        for wpg, wpc, lay, xcd in cands:
+        for wpg, wpc, lay, xcd, strip in cands:
             for graph in (0, 1):
-                self.plan.set_tuning(R.Tuning(wpg, wpc, graph, lay, xcd))
+                self.plan.set_tuning(R.Tuning(wpg, wpc, graph, lay, xcd, strip))
                 ms = sorted(event_time_ms(lambda i: self.plan.run(), reps) for _ in range(3))[1]
                 rows.append({"layout": LAYOUT_NAME[lay], "waves_per_wg": wpg, "wgs_per_cu": wpc,
-                             "xcd_ranges": bool(xcd), "graph": bool(graph), "ms": round(ms, 4)})
+                             "xcd_ranges": bool(xcd), "strip": strip, "graph": bool(graph),
+                             "ms": round(ms, 4)})
         self.plan.set_tuning(keep)
         return sorted(rows, key=lambda r: r["ms"])
 
@@ -1085,6 +1093,9 @@ def main():
                     help="ragged: skip the frame and single-plane figures added to the line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="ragged, sweep: use the tuning cache (or defaults) instead of tuning first")
+    ap.add_argument("--geometry", default=None, metavar="WPGxWPC:XCD:STRIP",
+                    help="ragged, sweep: run the strided layout at this geometry (e.g. 1x4:1:2) "
+                         "instead of tuning (profiles of one geometry)")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests in the served trace (2000 req/s; 0 = skip the serving leg; "
                          "default 4000 with the ragged workload, else 0)")
@@ -1119,14 +1130,21 @@ def main():
     from paper_1402_6034_amd import rdct as R
     R.lib()
     torch.cuda.init()
+    tune = not args.no_autotune and args.geometry is None
     if args.workload == "ragged":
-        wl = RaggedBatch(planes_cache=args.planes_cache, autotune=not args.no_autotune)
+        wl = RaggedBatch(planes_cache=args.planes_cache, autotune=tune)
     elif args.workload == "sweep":
-        wl = RetentionSweep(autotune=not args.no_autotune, planes_cache=args.planes_cache)
+        wl = RetentionSweep(autotune=tune, planes_cache=args.planes_cache)
     elif args.workload == "quality":
         wl = QualitySweep(planes_cache=args.planes_cache)
     else:
         wl = WORKLOADS[args.workload]()
+    if args.geometry is not None and args.workload in ("ragged", "sweep"):
+        size, xcd, strip = args.geometry.split(":")
+        wpg, wpc = (int(v) for v in size.split("x"))
+        wl.plan.set_tuning(R.Tuning(wpg, wpc, 0, R.LAYOUT_STRIDED, int(xcd), int(strip)))
+        log(f"[bench] geometry set: strided, {wpg} waves/WG x {wpc} WGs/CU, XCD ranges {xcd}, "
+            f"strip {strip}")
     if args.workload == "stream":
         wl.no_sweep = args.no_sweep
 

@@ -219,6 +219,9 @@ typedef struct {
                               range of work items, so neighbouring items share an
                               L2 (the default, and the order the autotuner times);
                               0 = the hardware's round-robin order                  */
+  int32_t strip;           /* STRIDED: consecutive 128-block work items a wave takes
+                              before striding, 1, 2, 4 or 8; 0 = from the tuning
+                              cache or default (explicit tunings only)              */
 } rdct_tuning_t;
 
 typedef struct rdct_batch_plan rdct_batch_plan_t;
@@ -268,9 +271,9 @@ rdct_status_t rdct_batch_plan_create_sweep(const rdct_plane_desc_t* planes, int3
 rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream);
 
 /* Run the plan with this geometry from now on (every field given, none taken
-   from the cache; not stored in the cache).  Errors: INVALID_ARG (not a valid
-   geometry: waves_per_wg 1, 2 or 4, wgs_per_cu 1..16, a known layout,
-   xcd_ranges 0 or 1). */
+   from the cache, except that strip 0 means 1; not stored in the cache).
+   Errors: INVALID_ARG (not a valid geometry: waves_per_wg 1, 2 or 4,
+   wgs_per_cu 1..16, a known layout, xcd_ranges 0 or 1, strip 1, 2, 4 or 8). */
 rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tuning_t* tuning);
 
 /* Blocks and work items of a plan, and the geometry it runs with (any pointer

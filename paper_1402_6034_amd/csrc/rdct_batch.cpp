@@ -108,7 +108,7 @@ hipError_t launch_direct(rdct_batch_plan* p, const rdct_tuning_t& t, hipStream_t
     } else {
       e = launch_batch(p->sel, p->co, p->recon, g.ev, p->d_planes + g.plane0, p->d_tables,
                        p->d_items + g.item0, g.n_items, grid_of(p, g, t), t.waves_per_wg, s,
-                       nullptr, t.xcd_ranges);
+                       nullptr, t.xcd_ranges, t.strip);
     }
     if (e != hipSuccess) return e;
   }
@@ -292,6 +292,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
   // so boundary lines are read once (the ragged batch reads 1.05x its planes
   // this way against 1.18x in the hardware's order, at the same or better speed).
   t.xcd_ranges = 1;
+  t.strip = 1;
   rdct_tuning_t cached;
   if (tune_cache_lookup(p->key, &cached)) {
     rdct_tuning_t c = t;
@@ -299,6 +300,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     c.wgs_per_cu = cached.wgs_per_cu;
     c.layout = cached.layout;
     c.xcd_ranges = cached.xcd_ranges;
+    c.strip = cached.strip;
     if (valid_tuning(c)) t = c;
   }
   if (tuning) {
@@ -307,6 +309,7 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
     if (tuning->layout) t.layout = tuning->layout;
     t.use_graph = tuning->use_graph ? 1 : 0;
     t.xcd_ranges = tuning->xcd_ranges;
+    if (tuning->strip) t.strip = tuning->strip;
   }
   if (!valid_tuning(t)) {
     delete p;
@@ -342,6 +345,57 @@ rdct_status_t create_plan(const rdct_plane_desc_t* planes, int32_t n, rdct_coef_
 
 }  // namespace
 
+// Median time (us per run) of each candidate geometry on this plan.  Each
+// candidate gets one untimed launch, then kRounds rounds; a round queues `reps`
+// launches of every candidate in turn, back to back with no synchronisation in
+// between (as runs follow each other in use), an event before and after each
+// candidate's launches, and waits once at its end.  A drift of the clock or
+// temperature during the search thus weighs on every candidate alike, the GPU
+// never idles between candidates, and a candidate's median round decides.
+// Timing single launches between synchronisations ranked the ragged batch's
+// geometries differently from back-to-back runs (1.35 against 1.31 ms for the
+// pick), and so did short rounds that each began after a synchronisation.
+// Invalid candidates are dropped from `cands` first.
+static rdct_status_t time_candidates(rdct_batch_plan* plan, std::vector<rdct_tuning_t>& cands,
+                                     int reps, hipStream_t s, std::vector<float>* med) {
+  cands.erase(std::remove_if(cands.begin(), cands.end(),
+                             [](const rdct_tuning_t& t) { return !valid_tuning(t); }),
+              cands.end());
+  if (cands.empty()) return RDCT_ERR_INVALID_ARG;
+  constexpr int kRounds = 5;
+  const size_t nc = cands.size();
+  std::vector<hipEvent_t> ev(nc + 1, nullptr);
+  std::vector<std::vector<float>> us(nc);
+  rdct_status_t st = RDCT_OK;
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = RDCT_ERR_HIP;
+  for (size_t c = 0; c < nc && st == RDCT_OK; ++c)
+    if (launch_direct(plan, cands[c], s) != hipSuccess) st = RDCT_ERR_HIP;
+  for (int round = 0; round < kRounds && st == RDCT_OK; ++round) {
+    bool ok = hipEventRecord(ev[0], s) == hipSuccess;
+    for (size_t c = 0; c < nc && ok; ++c) {
+      for (int r = 0; r < reps && ok; ++r) ok = launch_direct(plan, cands[c], s) == hipSuccess;
+      ok = ok && hipEventRecord(ev[c + 1], s) == hipSuccess;
+    }
+    ok = ok && hipEventSynchronize(ev[nc]) == hipSuccess;
+    for (size_t c = 0; c < nc && ok; ++c) {
+      float ms = 0.f;
+      ok = hipEventElapsedTime(&ms, ev[c], ev[c + 1]) == hipSuccess;
+      us[c].push_back(ms * 1000.f / reps);
+    }
+    if (!ok) st = RDCT_ERR_HIP;
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st != RDCT_OK) return st;
+  med->assign(nc, 0.f);
+  for (size_t c = 0; c < nc; ++c) {
+    std::sort(us[c].begin(), us[c].end());
+    (*med)[c] = us[c][us[c].size() / 2];
+  }
+  return RDCT_OK;
+}
+
 extern "C" {
 
 rdct_status_t rdct_batch_plan_create(const rdct_plane_desc_t* planes, int32_t n,
@@ -370,8 +424,10 @@ rdct_status_t rdct_batch_run(rdct_batch_plan_t* plan, void* stream) {
 }
 
 rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tuning_t* tuning) {
-  if (!plan || !tuning || !valid_tuning(*tuning)) return RDCT_ERR_INVALID_ARG;
+  if (!plan || !tuning) return RDCT_ERR_INVALID_ARG;
   rdct_tuning_t t = *tuning;
+  if (t.strip == 0) t.strip = 1;   // the field added last: 0 reads as one item
+  if (!valid_tuning(t)) return RDCT_ERR_INVALID_ARG;
   t.use_graph = t.use_graph ? 1 : 0;
   plan->tuning = t;
   plan->graph_ready = false;  // re-captured on the next run when use_graph
@@ -391,10 +447,10 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
                                   rdct_tuning_t* best) {
   if (!plan || reps < 1 || reps > 1000) return RDCT_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  // Candidates: the strided layout (in the XCD-range order, which reads fewer
-  // bytes and measured as fast or faster at every geometry from 4 resident
-  // waves per CU up) over waves per workgroup x resident waves per CU, and the
-  // per-plane layout over waves per workgroup.
+  // Stage 1, the geometry: the strided layout (in the XCD-range order, which
+  // reads fewer bytes and measured as fast or faster at every geometry from 4
+  // resident waves per CU up; one item per strip) over waves per workgroup x
+  // resident waves per CU, and the per-plane layout over waves per workgroup.
   std::vector<rdct_tuning_t> cands;
   for (int wpg : {1, 2, 4}) {
     for (int waves : {2, 4, 8, 12, 16}) {
@@ -404,6 +460,7 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
       t.waves_per_wg = wpg;
       t.wgs_per_cu = waves / wpg;
       t.xcd_ranges = 1;
+      t.strip = 1;
       cands.push_back(t);
     }
     rdct_tuning_t t = plan->tuning;
@@ -411,64 +468,23 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
     t.waves_per_wg = wpg;
     t.wgs_per_cu = 1;
     t.xcd_ranges = 0;
+    t.strip = 1;
     cands.push_back(t);
   }
-  cands.erase(std::remove_if(cands.begin(), cands.end(),
-                             [](const rdct_tuning_t& t) { return !valid_tuning(t); }),
-              cands.end());
-  // Each candidate gets one untimed launch, then kRounds rounds; a round
-  // queues `reps` launches of every candidate in turn, back to back with no
-  // synchronisation in between (as runs follow each other in use), an event
-  // before and after each candidate's launches, and waits once at its end.  A
-  // drift of the clock or temperature during the search thus weighs on every
-  // candidate alike, the GPU never idles between candidates, and a candidate's
-  // median round decides.  Timing single launches between synchronisations
-  // ranked the ragged batch's geometries differently from back-to-back runs
-  // (1.35 against 1.31 ms for the pick), and so did short rounds that each
-  // began after a synchronisation.
-  constexpr int kRounds = 5;
-  const size_t nc = cands.size();
-  std::vector<hipEvent_t> ev(nc + 1, nullptr);
-  std::vector<std::vector<float>> us(nc);
-  rdct_status_t st = RDCT_OK;
-  for (hipEvent_t& e : ev)
-    if (hipEventCreate(&e) != hipSuccess) st = RDCT_ERR_HIP;
-  for (size_t c = 0; c < nc && st == RDCT_OK; ++c)
-    if (launch_direct(plan, cands[c], s) != hipSuccess) st = RDCT_ERR_HIP;
-  for (int round = 0; round < kRounds && st == RDCT_OK; ++round) {
-    bool ok = hipEventRecord(ev[0], s) == hipSuccess;
-    for (size_t c = 0; c < nc && ok; ++c) {
-      for (int r = 0; r < reps && ok; ++r) ok = launch_direct(plan, cands[c], s) == hipSuccess;
-      ok = ok && hipEventRecord(ev[c + 1], s) == hipSuccess;
-    }
-    ok = ok && hipEventSynchronize(ev[nc]) == hipSuccess;
-    for (size_t c = 0; c < nc && ok; ++c) {
-      float ms = 0.f;
-      ok = hipEventElapsedTime(&ms, ev[c], ev[c + 1]) == hipSuccess;
-      us[c].push_back(ms * 1000.f / reps);
-    }
-    if (!ok) st = RDCT_ERR_HIP;
-  }
-  for (hipEvent_t e : ev)
-    if (e) (void)hipEventDestroy(e);
+  std::vector<float> med;
+  rdct_status_t st = time_candidates(plan, cands, reps, s, &med);
   if (st != RDCT_OK) return st;
-  std::vector<float> med(nc);
-  float fastest = 1e30f;
-  for (size_t c = 0; c < nc; ++c) {
-    std::sort(us[c].begin(), us[c].end());
-    med[c] = us[c][us[c].size() / 2];
-    fastest = std::min(fastest, med[c]);
-  }
+  const float fastest = *std::min_element(med.begin(), med.end());
   // Among the candidates within 2% of the fastest, the fewest resident waves
   // per CU (then the faster).  On the ragged batch the geometries from 4 to 16
   // resident waves land within 2-3% of each other in such short rounds, in an
-  // order that changes from run to run, while runs of hundreds of plans at a
+  // order that changed from run to run, while runs of hundreds of plans at a
   // time measured 1 x 4 at 1.30-1.31 ms against 1.33-1.35 ms for 4 x 3 or
   // 1 x 12.
   float best_us = 1e30f;
   int best_waves = 1 << 30;
   rdct_tuning_t best_t = plan->tuning;
-  for (size_t c = 0; c < nc; ++c) {
+  for (size_t c = 0; c < cands.size(); ++c) {
     if (med[c] > fastest * 1.02f) continue;
     // Resident waves per CU: the strided grid holds wgs_per_cu workgroups per
     // CU; the per-plane grid one workgroup per plane.
@@ -482,6 +498,22 @@ rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* s
       best_us = med[c];
       best_t = cands[c];
     }
+  }
+  // Stage 2, the strip of the strided pick: consecutive items per wave.  Two
+  // took the ragged batch from 1.305 to 1.260 ms (a wave writes longer runs of
+  // neighbouring output), although its reads rose from 1.05x to 1.14x the
+  // planes.
+  if (best_t.layout == RDCT_LAYOUT_STRIDED) {
+    std::vector<rdct_tuning_t> strips;
+    for (int strip : {1, 2, 4, 8}) {
+      rdct_tuning_t t = best_t;
+      t.strip = strip;
+      strips.push_back(t);
+    }
+    if ((st = time_candidates(plan, strips, reps, s, &med)) != RDCT_OK) return st;
+    const size_t k = std::min_element(med.begin(), med.end()) - med.begin();
+    best_t = strips[k];
+    best_us = med[k];
   }
   plan->tuning = best_t;
   plan->graph_ready = false;  // re-captured on the next run

@@ -49,7 +49,8 @@ inline bool valid_tuning(const rdct_tuning_t& t) {
   return (t.waves_per_wg == 1 || t.waves_per_wg == 2 || t.waves_per_wg == 4) &&
          t.wgs_per_cu >= 1 && t.wgs_per_cu <= 16 &&
          (t.layout == RDCT_LAYOUT_STRIDED || t.layout == RDCT_LAYOUT_PER_PLANE) &&
-         (t.xcd_ranges == 0 || t.xcd_ranges == 1);
+         (t.xcd_ranges == 0 || t.xcd_ranges == 1) &&
+         (t.strip == 1 || t.strip == 2 || t.strip == 4 || t.strip == 8);
 }
 
 // Work list of planes 0 .. n-1 (nblocks[i] blocks each): plane i's items are

@@ -131,7 +131,8 @@ hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes
                         const QuantConsts* tables,
                         const WorkItem* items, int32_t n_items, int32_t grid,
                         int32_t waves_per_wg, hipStream_t stream,
-                        const int32_t* first = nullptr, int xcd = 0);  // xcd: see xcd_remap
+                        const int32_t* first = nullptr, int xcd = 0,  // xcd: see xcd_remap
+                        int strip = 1);  // strided layout: consecutive items per wave
 
 // Compute units of the current device (looked up on every call).
 int device_cu_count();

@@ -759,7 +759,7 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
                                                   const QuantConsts* __restrict__ tables,
                                                   const WorkItem* __restrict__ items,
                                                   int n_items, const int* __restrict__ first,
-                                                  int xcd) {
+                                                  int xcd, int strip) {
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -824,15 +824,17 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
     return;
   }
 
+  // Wave w takes the strip of `strip` consecutive items starting at item
+  // w * strip, then strides by the grid's waves x strip.
   const int b = xcd ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-  int it = b * wpg + wave;
+  const int it = (b * wpg + wave) * strip;
   if (it >= n_items) return;
   // The wave's error parts accumulate while its items stay in one plane and are
   // written when the plane changes: a large plane gets one atomic per wave
   // rather than one per item, all on the same address.
   uint64_t acc = 0;
   int acc_plane = items[it].plane;
-  run_items(it, n_waves, n_items, [&](int plane, uint64_t part) {
+  auto add_part = [&](int plane, uint64_t part) {
     if constexpr (EV != EV_NONE) {
       if (plane != acc_plane) {
         flush_sums<EV>(planes[acc_plane], acc, lane);
@@ -841,7 +843,13 @@ __device__ __forceinline__ void batch_kernel_body(const Plane* __restrict__ plan
       }
       acc += part;
     }
-  });
+  };
+  if (strip == 1) {
+    run_items(it, n_waves, n_items, add_part);
+  } else {
+    for (int s0 = it; s0 < n_items; s0 += n_waves * strip)
+      run_items(s0, 1, min(s0 + strip, n_items), add_part);
+  }
   if constexpr (EV != EV_NONE) flush_sums<EV>(planes[acc_plane], acc, lane);
 }
 
@@ -849,8 +857,9 @@ template <int SEL, int CO, bool RECON, int EV>
 __global__ __launch_bounds__(256, 2) void k_batch(const Plane* __restrict__ planes,
                                                   const QuantConsts* __restrict__ tables,
                                                   const WorkItem* __restrict__ items, int n_items,
-                                                  const int* __restrict__ first, int xcd) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd);
+                                                  const int* __restrict__ first, int xcd,
+                                                  int strip) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd, strip);
 }
 
 template <int SEL, int CO, bool RECON, int EV>
@@ -858,8 +867,8 @@ __global__ __launch_bounds__(256, 1) void k_batch_w(const Plane* __restrict__ pl
                                                     const QuantConsts* __restrict__ tables,
                                                     const WorkItem* __restrict__ items,
                                                     int n_items, const int* __restrict__ first,
-                                                    int xcd) {
-  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd);
+                                                    int xcd, int strip) {
+  batch_kernel_body<SEL, CO, RECON, EV>(planes, tables, items, n_items, first, xcd, strip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,7 +1025,7 @@ static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg,
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
                                  const WorkItem* items, int n_items, const int* first,
-                                 int grid, int wpg, int xcd, hipStream_t s) {
+                                 int grid, int wpg, int xcd, int strip, hipStream_t s) {
   static_assert(Stage<CO>::wave_bytes % 8 == 0 && kReconStageBytes % 8 == 0,
                 "stages keep the per-plane sums area 8-byte aligned");
   const size_t lds = (EV == EV_SWEEP ? (size_t)wpg * 64 * 65 * 4 : 0) +
@@ -1024,10 +1033,10 @@ static hipError_t launch_batch_t(const Plane* planes, const QuantConsts* tables,
                      (first != nullptr && EV != EV_NONE ? (size_t)wpg * 64 * 8 : 0);
   if constexpr (WideRegs<SEL, CO, RECON, EV>::value)
     hipLaunchKernelGGL((k_batch_w<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items, first, xcd);
+                       tables, items, n_items, first, xcd, strip);
   else
     hipLaunchKernelGGL((k_batch<SEL, CO, RECON, EV>), dim3(grid), dim3(64 * wpg), lds, s, planes,
-                       tables, items, n_items, first, xcd);
+                       tables, items, n_items, first, xcd, strip);
   return hipGetLastError();
 }
 
@@ -1076,9 +1085,10 @@ hipError_t launch_plane(int sel, int co, bool recon, int ev, const Plane& P,
 hipError_t launch_batch(int sel, int co, bool recon, int ev, const Plane* planes,
                         const QuantConsts* tables, const WorkItem* items,
                         int32_t n_items, int32_t grid, int32_t wpg, hipStream_t s,
-                        const int32_t* first, int xcd) {
+                        const int32_t* first, int xcd, int strip) {
   if (n_items <= 0) return hipSuccess;
-  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, first, grid, wpg, xcd, s)
+  if (strip < 1) strip = 1;
+  RDCT_DISPATCH(launch_batch_t, planes, tables, items, n_items, first, grid, wpg, xcd, strip, s)
 }
 
 hipError_t launch_inverse(int kind, const void* coef, int32_t width, int32_t height, int32_t r,

@@ -22,6 +22,7 @@ struct Entry {
   int wgs_per_cu = 0;
   int layout = 0;
   int xcd_ranges = 0;
+  int strip = 1;
   float us = 0.f;
 };
 
@@ -52,6 +53,7 @@ std::map<std::string, Entry> load(const std::string& path) {
       continue;
     if (!scan_int(line, "layout", &en.layout)) en.layout = RDCT_LAYOUT_STRIDED;
     if (!scan_int(line, "xcd_ranges", &en.xcd_ranges)) en.xcd_ranges = 0;
+    if (!scan_int(line, "strip", &en.strip)) en.strip = 1;
     const size_t u = line.find("\"us\": ");
     if (u != std::string::npos) en.us = (float)atof(line.c_str() + u + 6);
     m[line.substr(b, e - b)] = en;
@@ -84,6 +86,7 @@ bool tune_cache_lookup(const std::string& key, rdct_tuning_t* out) {
   out->use_graph = 0;
   out->layout = it->second.layout;
   out->xcd_ranges = it->second.xcd_ranges;
+  out->strip = it->second.strip;
   return true;
 }
 
@@ -91,7 +94,7 @@ void tune_cache_store(const std::string& key, const rdct_tuning_t& t, float us) 
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string path = tune_cache_path();
   auto m = load(path);
-  m[key] = Entry{t.waves_per_wg, t.wgs_per_cu, t.layout, t.xcd_ranges, us};
+  m[key] = Entry{t.waves_per_wg, t.wgs_per_cu, t.layout, t.xcd_ranges, t.strip, us};
   mkdirs_for(path);
   const std::string tmp = path + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
@@ -101,9 +104,9 @@ void tune_cache_store(const std::string& key, const rdct_tuning_t& t, float us) 
   for (const auto& kv : m) {
     fprintf(f,
             "  {\"key\": \"%s\", \"waves_per_wg\": %d, \"wgs_per_cu\": %d, \"layout\": %d, "
-            "\"xcd_ranges\": %d, \"us\": %.3f}%s\n",
+            "\"xcd_ranges\": %d, \"strip\": %d, \"us\": %.3f}%s\n",
             kv.first.c_str(), kv.second.waves_per_wg, kv.second.wgs_per_cu, kv.second.layout,
-            kv.second.xcd_ranges, kv.second.us, ++i < m.size() ? "," : "");
+            kv.second.xcd_ranges, kv.second.strip, kv.second.us, ++i < m.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);

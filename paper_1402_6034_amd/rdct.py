@@ -100,7 +100,7 @@ class PlaneDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """rdct_tuning_t."""
     _fields_ = [("waves_per_wg", c_int32), ("wgs_per_cu", c_int32), ("use_graph", c_int32),
-                ("layout", c_int32), ("xcd_ranges", c_int32)]
+                ("layout", c_int32), ("xcd_ranges", c_int32), ("strip", c_int32)]
 
 
 class QualityDesc(ctypes.Structure):

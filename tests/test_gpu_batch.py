@@ -223,17 +223,18 @@ def test_many_small_sweep_planes(layout):
     plan.close()
 
 
-@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("xcd,strip", [(0, 1), (1, 1), (1, 2), (0, 4), (1, 8)])
 @pytest.mark.parametrize("wpg,wpc", [(1, 4), (2, 3), (4, 1)])
-def test_xcd_ranges_give_identical_outputs(xcd, wpg, wpc):
-    # The XCD-range order of the strided layout changes which wave runs which
-    # item, never a result: every output equals the single-plane call's.
+def test_xcd_ranges_and_strips_give_identical_outputs(xcd, strip, wpg, wpc):
+    # The XCD-range order and the strip of the strided layout change which wave
+    # runs which item, never a result: every output equals the single-plane
+    # call's.
     imgs, dev, rng = ragged_planes(37, 9, full_blocks=False)
     quals = [int(q) for q in rng.integers(10, 91, size=len(imgs))]
     sels = [R.select(R.SEL_QUANT, quality=q, level_shift=128) for q in quals]
     plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True,
-                       tuning=R.Tuning(wpg, wpc, 0, R.LAYOUT_STRIDED, xcd))
-    assert plan.tuning.xcd_ranges == xcd
+                       tuning=R.Tuning(wpg, wpc, 0, R.LAYOUT_STRIDED, xcd, strip))
+    assert plan.tuning.xcd_ranges == xcd and plan.tuning.strip == strip
     for _ in range(2):
         plan.run()
     sse = host(plan.sse)
@@ -245,24 +246,26 @@ def test_xcd_ranges_give_identical_outputs(xcd, wpg, wpc):
     # A geometry set on the existing plan (here graph replay, the other XCD
     # order and the per-plane layout) gives the same outputs.
     coef0, recon0 = host(plan.coef).copy(), host(plan.recon).copy()
-    for t in (R.Tuning(wpg, wpc, 1, R.LAYOUT_STRIDED, 1 - xcd), R.Tuning(4, 1, 0, R.LAYOUT_PER_PLANE, 0)):
+    for t in (R.Tuning(wpg, wpc, 1, R.LAYOUT_STRIDED, 1 - xcd, 1 if strip > 1 else 4),
+              R.Tuning(4, 1, 0, R.LAYOUT_PER_PLANE, 0)):
         plan.set_tuning(t)
         plan.sse.fill_(7)
         plan.run()
         plan.run()
         assert np.array_equal(host(plan.sse), sse)
         assert np.array_equal(host(plan.coef), coef0) and np.array_equal(host(plan.recon), recon0)
-    with pytest.raises(R.RdctError):
-        plan.set_tuning(R.Tuning(3, 4, 0, R.LAYOUT_STRIDED, 0))
+    for bad in (R.Tuning(3, 4, 0, R.LAYOUT_STRIDED, 0), R.Tuning(1, 4, 0, R.LAYOUT_STRIDED, 1, 3)):
+        with pytest.raises(R.RdctError):
+            plan.set_tuning(bad)
     plan.close()
 
 
 @pytest.mark.parametrize("tuning", [(3, 4, 0, 1), (1, 17, 0, 1), (1, 4, 0, 3), (2, 0, 0, -1),
-                                    (1, 4, 0, 1, 2)])
+                                    (1, 4, 0, 1, 2), (1, 4, 0, 1, 1, 16), (1, 4, 0, 1, 1, -2)])
 def test_invalid_tuning_rejected(tuning):
     """Waves per workgroup outside 1, 2, 4, resident workgroups outside 1..16,
-    unknown layouts and XCD-range flags other than 0 and 1 are refused at plan
-    creation (nothing is launched)."""
+    unknown layouts, XCD-range flags other than 0 and 1 and strips other than
+    1, 2, 4, 8 are refused at plan creation (nothing is launched)."""
     imgs, dev, _ = ragged_planes(2, 8)
     sels = [R.select(R.SEL_ZIGZAG, r=5)] * 2
     with pytest.raises(R.RdctError) as e:

@@ -209,7 +209,12 @@ static void checks() {
   t.waves_per_wg = 4;
   t.wgs_per_cu = 16;
   t.layout = RDCT_LAYOUT_PER_PLANE;
+  CHECK(!valid_tuning(t));   // strip 0 is not a geometry
+  t.strip = 8;
   CHECK(valid_tuning(t));
+  t.strip = 3;
+  CHECK(!valid_tuning(t));
+  t.strip = 1;
   t.waves_per_wg = 3;
   CHECK(!valid_tuning(t));
   t.waves_per_wg = 1;
@@ -238,13 +243,15 @@ static void tune_cache(const char* path) {
   rdct_tuning_t t{};
   CHECK(tune_cache_lookup("gfx950/ok", &t));
   CHECK(t.waves_per_wg == 2 && t.wgs_per_cu == 8 && t.layout == 2 && t.use_graph == 0);
+  CHECK(t.strip == 1);   // entries written before the strip existed
   CHECK(!tune_cache_lookup("unterminated", &t));
   rdct_tuning_t u{};
   u.waves_per_wg = 4;
   u.wgs_per_cu = 3;
   u.layout = 1;
+  u.strip = 4;
   tune_cache_store("gfx950/new", u, 12.5f);
-  CHECK(tune_cache_lookup("gfx950/new", &t) && t.wgs_per_cu == 3);
+  CHECK(tune_cache_lookup("gfx950/new", &t) && t.wgs_per_cu == 3 && t.strip == 4);
   CHECK(tune_cache_lookup("gfx950/ok", &t) && t.wgs_per_cu == 8);
 }
 
