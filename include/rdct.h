@@ -281,14 +281,16 @@ rdct_status_t rdct_batch_plan_set_tuning(rdct_batch_plan_t* plan, const rdct_tun
 rdct_status_t rdct_batch_plan_info(const rdct_batch_plan_t* plan, int64_t* n_blocks,
                                    int32_t* n_items, rdct_tuning_t* used);
 
-/* Time every candidate geometry on this plan (both layouts; five rounds that
-   each queue reps launches of every candidate in turn, back to back, timed with
-   HIP events between candidates; a candidate's median round is its time;
-   synchronous), adopt, among the candidates within 2% of the fastest, the one
-   with the fewest resident waves per CU (then the faster),
-   store it in the tuning cache (file named by RDCT_TUNING_CACHE, default
-   ~/.cache/rdct_tuning.json, keyed by architecture, path variant, size class
-   and plane-count class) and return it in *best. */
+/* Tune the plan's geometry by timing it on the plan (synchronous).  Timing:
+   five rounds that each queue reps launches of every candidate in turn, back
+   to back, with HIP events between candidates; a candidate's median round is
+   its time.  Stage 1 times both layouts over waves per workgroup and resident
+   waves per CU (strip 1) and takes, among the candidates within 2% of the
+   fastest, the one with the fewest resident waves per CU (then the faster);
+   for a strided pick, stage 2 times strips 1, 2, 4 and 8 and takes the
+   fastest.  The result is adopted, stored in the tuning cache (file named by
+   RDCT_TUNING_CACHE, default ~/.cache/rdct_tuning.json, keyed by architecture,
+   path variant, size class and plane-count class) and returned in *best. */
 rdct_status_t rdct_batch_autotune(rdct_batch_plan_t* plan, int32_t reps, void* stream,
                                   rdct_tuning_t* best);
 
