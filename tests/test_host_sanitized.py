@@ -5,7 +5,7 @@ admission (metadata and plane budgets, including a budget that leaves less
 than one request's metadata), the work lists and plane ordering of batch plans,
 the plane and geometry checks, the host-side metrics (PSNR of many planes,
 quality metrics, pair decoding) and the tuning-cache parser on malformed files.
-Any sanitizer report aborts the driver and fails the test."""
+Any sanitizer report aborts the test program and fails the test."""
 import os
 import shutil
 import subprocess
