@@ -28,6 +28,8 @@ void fill_quant_consts(const uint16_t q[64], QuantConsts* out) {
     }
     out->dq[kl] = Q * scale_kl(k, l);
     out->qi[kl] = (int32_t)q[kl];
+    const double f = quant_multiplier(kGram[k], kGram[l], q[kl]);
+    memcpy(&out->qf[kl], &f, 8);
   }
 }
 

@@ -131,6 +131,16 @@ __device__ __forceinline__ int quantize(int y, uint64_t qm) {
   }
 }
 
+// The same q from the low word of one float64 FMA, Y * qf + 1.5 * 2^52, with
+// qf from quant_multiplier: the addend pins the exponent, so the FMA's single
+// rounding is to the nearest integer and leaves q (two's complement) in the low
+// 32 bits.  Three instructions per coefficient (extract, convert, FMA) against
+// five or six above.
+__device__ __forceinline__ int quantize_fma(int y, uint64_t qf) {
+  const double t = __builtin_fma((double)y, __longlong_as_double((long long)qf), 0x1.8p52);
+  return (int)(uint32_t)__double_as_longlong(t);
+}
+
 // ---------------------------------------------------------------------------
 // Block loads (8 rows x 8 bytes), edge-replicating partial blocks.
 // ---------------------------------------------------------------------------

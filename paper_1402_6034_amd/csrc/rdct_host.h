@@ -4,6 +4,7 @@
 // it also builds on its own, with the address and undefined-behaviour
 // sanitizers, for tests on a machine without a GPU.
 #pragma once
+#include <math.h>
 #include <stdint.h>
 
 #include <iterator>
@@ -23,6 +24,21 @@ struct WorkItem {
   int32_t plane;
   int32_t t0;
 };
+
+// Multiplier m of the exact quantiser q = round(Y / (Q sqrt(g_k g_l))), halves
+// away from zero (Section 3 quantises the orthogonal coefficients S Y S with the
+// JPEG tables; g_k, g_l are diagonal entries of C0 C0^T, Section 2).  The
+// kernels take q from the low word of the float64 FMA Y * m + 1.5 * 2^52, whose
+// one rounding is to the nearest integer.  Where g_k == g_l the quotient
+// Y / (g_k Q) is rational and can be a tie: m = 1 / (g_k Q) is then raised by a
+// relative 2^-32, so a tie lies beyond the half-integer away from zero while
+// every other value (at least 1 / (2 g_k Q) from a half-integer, |Y| < 2^15)
+// keeps its side.  Elsewhere the quotient is irrational and at least ~4e-9 from
+// any half-integer (Q <= 255), far above the float64 error of m.
+inline double quant_multiplier(int gk, int gl, int Q) {
+  if (gk == gl) return (1.0 / ((double)gk * (double)Q)) * (1.0 + 0x1p-32);
+  return 1.0 / ((double)Q * sqrt((double)gk * (double)gl));
+}
 
 // Number of 8x8 blocks of a w x h plane (partial blocks included).
 inline int64_t blocks_of(int32_t w, int32_t h) {

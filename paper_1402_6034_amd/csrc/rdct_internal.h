@@ -34,10 +34,12 @@ struct Plane {
 //          bits of 1 / (Q sqrt(g_k g_l)).
 //  dq[kl]  Q sqrt(1/(g_k g_l)) in float64 (dequantise and scale in one factor).
 //  qi[kl]  Q itself (integer), for the coefficient-domain error z - q Q.
+//  qf[kl]  float64 bits of quant_multiplier (the FMA form of the quantiser).
 struct QuantConsts {
   uint64_t qm[64];
   double dq[64];
   int32_t qi[64];
+  uint64_t qf[64];
 };
 
 // Comparison transforms: forward matrix F (block -> F A F^T) and inverse basis

@@ -176,10 +176,11 @@ __device__ __forceinline__ uint64_t qerr_units(const QErr& e) {
 }
 
 // Quantise one coefficient y at position KL; z = q Q (|z| < 2^15) for the inverse.
-template <int KL, bool ERR>
-__device__ __forceinline__ int quant_one(int y, uint64_t qm, int Q, QErr& e, int& z) {
+template <int KL, bool ERR, bool FQ>
+__device__ __forceinline__ int quant_one(int y, QCPtr qc, QErr& e, int& z) {
   constexpr int k = KL >> 3, l = KL & 7;
-  const int q = quantize<KL>(y, qm);
+  const int Q = qc->qi[KL];
+  const int q = FQ ? quantize_fma(y, qc->qf[KL]) : quantize<KL>(y, qc->qm[KL]);
   z = __mul24(q, Q);
   if constexpr (ERR) {
     if constexpr (rational_pos(k, l)) {
@@ -197,9 +198,10 @@ __device__ __forceinline__ int quant_one(int y, uint64_t qm, int Q, QErr& e, int
 }
 
 // Row K of block h of the pair: q goes to the lane's stage; with WB, q Q
-// replaces half h of the row's pairs (|q Q| < 2^15) for the inverse.  Returns a
-// value of the row's result, used to gate the table reads of a later row.
-template <int K, int CO, bool ERR, bool WB, int... L>
+// replaces half h of the row's pairs (|q Q| < 2^15) for the inverse.  FQ picks
+// the FMA form of the quantiser.  Returns a value of the row's result, used to
+// gate the table reads of a later row.
+template <int K, int CO, bool ERR, bool WB, bool FQ, int... L>
 __device__ __forceinline__ uint32_t quant_row(s16x2 (&row)[8], int h, QCPtr qc, uint8_t* stage,
                                               QErr& e, std::integer_sequence<int, L...>) {
   int q[8];
@@ -209,7 +211,7 @@ __device__ __forceinline__ uint32_t quant_row(s16x2 (&row)[8], int h, QCPtr qc, 
     constexpr int l = decltype(lc)::value;
     constexpr int kl = K * 8 + l;
     int z;
-    q[l] = quant_one<kl, ERR>(half(row[l], h), qc->qm[kl], qc->qi[kl], e, z);
+    q[l] = quant_one<kl, ERR, FQ>(half(row[l], h), qc, e, z);
     if constexpr (WB)
       row[l] = as_pair(__builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, row[l]), (uint32_t)z, put));
   };
@@ -221,14 +223,18 @@ __device__ __forceinline__ uint32_t quant_row(s16x2 (&row)[8], int h, QCPtr qc, 
   } else if constexpr (CO == CO_I16) {
     uint32_t d[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      d[m] = ((uint32_t)q[2 * m] & 0xffffu) | ((uint32_t)q[2 * m + 1] << 16);
+    for (int m = 0; m < 4; ++m) {
+      if constexpr (FQ)  // low halves of q[2m] (bits 0-15) and q[2m+1] (16-31)
+        d[m] = __builtin_amdgcn_perm((uint32_t)q[2 * m + 1], (uint32_t)q[2 * m], 0x05040100u);
+      else
+        d[m] = ((uint32_t)q[2 * m] & 0xffffu) | ((uint32_t)q[2 * m + 1] << 16);
+    }
     *reinterpret_cast<uint4*>(stage + K * 16) = make_uint4(d[0], d[1], d[2], d[3]);
   }
   return (uint32_t)q[7];
 }
 
-template <int CO, bool ERR, bool WB>
+template <int CO, bool ERR, bool WB, bool FQ>
 __device__ __forceinline__ void quant_rows(s16x2 (&v)[8][8], int h, QCPtr qc, uint8_t* stage,
                                            QErr& e) {
   QCPtr row_qc[8];
@@ -236,7 +242,7 @@ __device__ __forceinline__ void quant_rows(s16x2 (&v)[8][8], int h, QCPtr qc, ui
   row_qc[1] = qc;
   static_for<0, 8>([&](auto kc) {
     constexpr int K = decltype(kc)::value;
-    const uint32_t dep = quant_row<K, CO, ERR, WB>(v[K], h, row_qc[K], stage, e,
+    const uint32_t dep = quant_row<K, CO, ERR, WB, FQ>(v[K], h, row_qc[K], stage, e,
                                                    std::make_integer_sequence<int, 8>{});
     if constexpr (K + 2 < 8) row_qc[K + 2] = qc_after(qc, dep);
     // Finish the row (including its error terms) before the next one starts.
@@ -534,13 +540,18 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
     constexpr bool ERR = (EV == EV_COEF);
     constexpr bool SP = (EV == EV_SPATIAL);
     constexpr bool WB = RECON || SP;
+    // The FMA form of the quantiser everywhere but in the kernels that keep the
+    // pixels for a pixel-domain error.  Those keep the split form: with the FMA
+    // form, the strided batch kernel of that kind wrote wrong reconstructions
+    // of planes with partial blocks, and no cause was found in the source.
+    constexpr bool FQ = !SP;
     uint64_t s = 0;
     uint8_t* my_stage = stage_wave + lane * Stage<CO>::stride;
     // Quantise one block of the pair at a time through the lane's stage slot.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
       QErr e;
-      quant_rows<CO, ERR, WB>(v, h, qc_after_s(qc, h), my_stage, e);
+      quant_rows<CO, ERR, WB, FQ>(v, h, qc_after_s(qc, h), my_stage, e);
       if constexpr (ERR) {
         const uint64_t valid = (uint64_t)0 - (uint64_t)(h ? vh : vl);
         s += qerr_units(e) & valid;

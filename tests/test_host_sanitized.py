@@ -5,7 +5,8 @@ admission (metadata and plane budgets, including a budget that leaves less
 than one request's metadata), the work lists and plane ordering of batch plans,
 the plane and geometry checks, the host-side metrics (PSNR of many planes,
 quality metrics, pair decoding) and the tuning-cache parser on malformed files.
-Any sanitizer report aborts the test program and fails the test."""
+Any sanitizer report aborts the test program and fails the test.  A second
+program checks the quantiser's rule (multiplier and FMA) exhaustively."""
 import os
 import shutil
 import subprocess
@@ -335,3 +336,78 @@ def test_host_logic_under_sanitizers(driver, tmp_path):
     assert out.returncode == 0, out.stderr[-4000:]
     assert "runtime error" not in out.stderr and "AddressSanitizer" not in out.stderr
     assert out.stdout.strip() == "host logic ok"
+
+
+QUANT_RULE = r"""
+#include <stdio.h>
+#include <string.h>
+
+#include "rdct_host.h"
+
+// The kernels' quantiser: the low word of the float64 FMA y * m + 1.5 * 2^52.
+static int fma_quant(int y, double m) {
+  const double t = fma((double)y, m, 0x1.8p52);
+  uint64_t b;
+  memcpy(&b, &t, 8);
+  return (int)(uint32_t)b;
+}
+
+// q = round(y / (Q sqrt(gk gl))), halves away from zero, in integers: for a
+// rational quotient (gk == gl) from the remainder; otherwise j is the one value
+// with (2j - 1)^2 Q^2 gk gl < 4 y^2 < (2j + 1)^2 Q^2 gk gl.
+static long exact_quant(int y, int gk, int gl, int Q, long* ties) {
+  const long ay = y < 0 ? -(long)y : (long)y;
+  long j;
+  if (gk == gl) {
+    const long cq = (long)gk * Q;
+    j = (2 * ay + cq) / (2 * cq);
+    if ((2 * ay + cq) % (2 * cq) == 0) ++*ties;
+  } else {
+    const __int128 p = (__int128)Q * Q * gk * gl, v = (__int128)4 * ay * ay;
+    j = 0;
+    for (long step = 1L << 16; step; step >>= 1)
+      if ((__int128)(2 * (j + step) - 1) * (2 * (j + step) - 1) * p < v) j += step;
+    if ((__int128)(2 * j + 1) * (2 * j + 1) * p == v) return -1000000;  // a tie: impossible
+  }
+  return y < 0 ? -j : j;
+}
+
+int main() {
+  static const int g[3] = {8, 6, 4};
+  long checked = 0, ties = 0, bad = 0;
+  for (int Q = 1; Q <= 255; ++Q)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const double m = rdct::quant_multiplier(g[a], g[b], Q);
+        for (int y = -16384; y <= 16384; ++y, ++checked)
+          if (fma_quant(y, m) != exact_quant(y, g[a], g[b], Q, &ties)) {
+            if (bad++ < 5) fprintf(stderr, "Q=%d g=(%d,%d) y=%d\n", Q, g[a], g[b], y);
+          }
+      }
+  printf("%ld %ld %ld\n", checked, ties, bad);
+  return bad != 0;
+}
+"""
+
+
+def test_quantiser_rule_exhaustive(tmp_path):
+    """The kernels' quantiser (one float64 FMA with the multiplier the library
+    stores) against exact integer rounding, halves away from zero, of
+    Y / (Q sqrt(g_k g_l)) (Section 3's quantisation of the orthogonal
+    coefficients): every |Y| <= 2^14, every table entry 1..255, every pair of
+    diagonal entries of C0 C0^T, ties included."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "quant.cpp"
+    src.write_text(QUANT_RULE)
+    exe = tmp_path / "quant"
+    res = subprocess.run([gxx, "-std=c++17", "-O2", "-ffp-contract=off", "-Wall", "-I", CSRC,
+                          str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    checked, ties, bad = map(int, out.stdout.split())
+    assert checked == 255 * 9 * 32769
+    assert ties > 100000      # the rational positions' exact ties are exercised
+    assert bad == 0
