@@ -490,17 +490,24 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t s) {
 // ---------------------------------------------------------------------------
 // Pixels of one chunk as loaded by a lane: blocks t0 + lane (lo) and
 // t0 + 64 + lane (hi).
+// With `half`, the chunk is blocks t0 .. t0 + 63 only (the high blocks of the
+// pairs stay empty): a small plane then spreads over twice the waves.  nv0 / nv1
+// count the blocks of each half inside the plane (wave-uniform).
 struct Pixels {
   uint32_t al[16], ah[16];
   int xl, yl, xh, yh;
   int t0;
+  int nv0, nv1;
   bool vl, vh;
 };
 
-__device__ __forceinline__ void chunk_load(const Plane& P, int t0, int lane, Pixels& px) {
+__device__ __forceinline__ void chunk_load(const Plane& P, int t0, int lane, Pixels& px,
+                                           bool half = false) {
   px.t0 = t0;
-  px.vl = t0 + lane < P.nblocks;
-  px.vh = t0 + 64 + lane < P.nblocks;
+  px.nv0 = min(64, max(0, P.nblocks - t0));
+  px.nv1 = half ? 0 : min(64, max(0, P.nblocks - t0 - 64));
+  px.vl = lane < px.nv0;
+  px.vh = lane < px.nv1;
   load_block(P, t0 + lane, px.vl, px.al, px.xl, px.yl);
   load_block(P, t0 + 64 + lane, px.vh, px.ah, px.xh, px.yh);
 }
@@ -550,6 +557,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
     // Quantise one block of the pair at a time through the lane's stage slot.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
+      if ((h ? px.nv1 : px.nv0) == 0) continue;  // an empty half (small planes)
       QErr e;
       quant_rows<CO, ERR, WB, FQ>(v, h, qc_after_s(qc, h), my_stage, e);
       if constexpr (ERR) {
@@ -566,7 +574,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
         int ln = lane;
         asm volatile("" : "+v"(ln) : "s"(h));
         wave_sync();
-        flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), ln);
+        flush_stage<CO>(stage_wave, P.coef, first, h ? px.nv1 : px.nv0, ln);
         wave_sync();
       }
     }
@@ -575,6 +583,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
       // One block of the pair at a time keeps a single float64 row pass live.
 #pragma unroll 1
       for (int h = 0; h < 2; ++h) {
+        if ((h ? px.nv1 : px.nv0) == 0) continue;
         // The staged store is a wave-wide operation: every lane takes part, and
         // lanes past the end of the plane are masked at the store.
         if constexpr (!(RECON && EV == EV_COEF)) {
@@ -588,10 +597,8 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
         double err = 0.0;
         // EV_COEF is only used for planes made of whole blocks; those stage the
         // reconstruction.
-        const int first = t0 + 64 * h;
         quant_row_pass<RECON, SP, EV == EV_COEF>(P, v, h, a, h ? xh : xl, h ? yh : yl, err,
-                                                 stage_wave, lane,
-                                                 min(64, max(0, P.nblocks - first)));
+                                                 stage_wave, lane, h ? px.nv1 : px.nv0);
         if constexpr (SP) s += (uint64_t)__builtin_fma(err, 1048576.0, 0.5);
       }
     }
@@ -602,6 +609,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
     uint8_t* my_stage = stage_wave + lane * Stage<CO>::stride;
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
+      if ((h ? px.nv1 : px.nv0) == 0) continue;
       if (h ? vh : vl) {
         if constexpr (CO == CO_I32)
           store_i32(reinterpret_cast<int32_t*>(my_stage), v, keep, h);
@@ -612,7 +620,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
       }
       const int first = t0 + 64 * h;
       wave_sync();
-      flush_stage<CO>(stage_wave, P.coef, first, min(64, max(0, P.nblocks - first)), lane);
+      flush_stage<CO>(stage_wave, P.coef, first, h ? px.nv1 : px.nv0, lane);
       wave_sync();
     }
   }
@@ -625,15 +633,15 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
       const bool valid = h ? vh : vl;
+      if ((h ? px.nv1 : px.nv0) == 0) continue;
       // A staged store is a wave-wide operation: every lane takes part.
       if (!valid && !stage) continue;
       uint32_t a[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = h ? ah[i] : al[i];
-      const int first = t0 + 64 * h;
       const uint64_t e = retention_inverse<RECON, SP>(P, v, keep, a, h ? xh : xl, h ? yh : yl, h,
                                                       stage, stage_wave, lane,
-                                                      min(64, max(0, P.nblocks - first)));
+                                                      h ? px.nv1 : px.nv0);
       s += valid ? e : 0;
     }
     if constexpr (SP) return s;
@@ -693,25 +701,33 @@ struct Prefetch {
   static constexpr bool value = !RECON && (EV == EV_NONE || EV == EV_COEF || EV == EV_SWEEP);
 };
 
+// A plane of at most 128 blocks per CU (on 256 CUs) runs in chunks of 64
+// blocks, one per lane: its waves are few, each one's latency decides the
+// launch, and a chunk of 64 blocks halves the inverse and the stores per wave.
+__host__ __device__ constexpr bool half_chunks(int nblocks) { return nblocks <= 128 * 256; }
+
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void plane_kernel_body(const Plane& P, QCPtr qc) {
-  // Chunks of 128 blocks: wave w takes chunks w, w + W, ... (W waves in the
-  // grid).  Without error sums the grid covers the plane, one chunk per wave;
-  // with them the grid is capped, so a large plane's sums take one atomic per
-  // wave instead of one per chunk, all on the same address.
+  // Chunks of 128 blocks (64 on small planes, see half_chunks): wave w takes
+  // chunks w, w + W, ... (W waves in the grid).  Without error sums the grid
+  // covers the plane, one chunk per wave; with them the grid is capped, so a
+  // large plane's sums take one atomic per wave instead of one per chunk, all on
+  // the same address.
   extern __shared__ uint32_t lds[];
   const int wpg = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int n_waves = gridDim.x * wpg;
+  const bool half = half_chunks(P.nblocks);
+  const int cs = half ? 64 : 128;
   int c = blockIdx.x * wpg + wave;
-  if (c * 128 >= P.nblocks) return;
+  if (c * cs >= P.nblocks) return;
   uint8_t* stage = reinterpret_cast<uint8_t*>(lds + (EV == EV_SWEEP ? wpg * 64 * 65 : 0)) +
                    wave * wave_stage_bytes<SEL, CO, RECON, EV>();
   uint64_t acc = 0;
-  for (; c * 128 < P.nblocks; c += n_waves) {
+  for (; c * cs < P.nblocks; c += n_waves) {
     Pixels cur;
-    chunk_load(P, c * 128, lane, cur);
+    chunk_load(P, c * cs, lane, cur, half);
     acc += plane_chunk<SEL, CO, RECON, EV>(P, qc, cur, lane, lds + wave * (64 * 65), stage);
     if constexpr (EV == EV_NONE) break;
   }
@@ -1018,7 +1034,7 @@ constexpr int kPlaneWavesPerCU = 8;
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg, hipStream_t s) {
   const int n_cu = device_cu_count();
-  const int chunks = (P.nblocks + 127) / 128;
+  const int chunks = half_chunks(P.nblocks) ? (P.nblocks + 63) / 64 : (P.nblocks + 127) / 128;
   int grid = (chunks + wpg - 1) / wpg;
   if constexpr (EV != EV_NONE) {
     const int cap = n_cu * kPlaneWavesPerCU / wpg;

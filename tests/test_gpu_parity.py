@@ -233,6 +233,27 @@ def test_compress_eval_quant(h, w, quality):
     assert int(host(s2)[0]) == int(host(sse)[0])
 
 
+# Planes of at most 32768 blocks run in chunks of 64 blocks per wave (the high
+# block of every pair empty), larger ones in chunks of 128: both sides of that
+# rule, with whole and partial blocks.
+@pytest.mark.parametrize("h,w", [(1024, 2048), (1032, 2048), (1021, 2047), (1025, 2041)])
+def test_compress_eval_on_both_sides_of_the_chunk_rule(h, w):
+    img = plane(h, w, seed=h + w)
+    res = O.retention_eval(img, [10], recon_r=10)
+    sse, c32, rec = R.compress_eval(g(img), R.select(R.SEL_ZIGZAG, r=10), 1, R.COEF_I32, True)
+    assert int(host(sse)[0]) == res["sse_num"][10]
+    assert np.array_equal(host(c32), flat(res["Y"] * O.retention_mask(10)))
+    assert np.max(np.abs(host(rec) - res["recon"])) <= TOL
+    qt = O.quant_table(50)
+    qres = O.quant_eval(img, qt)
+    sel = R.select(R.SEL_QUANT, quality=50, level_shift=128)
+    sse, q, rec = R.compress_eval(g(img), sel, 1, R.COEF_I16, True)
+    assert np.array_equal(host(q).astype(np.int64), flat(qres["q"]))
+    assert np.max(np.abs(host(rec) - qres["recon"])) <= TOL
+    p = R.psnr_from_sse(int(host(sse)[0]), R.SEL_QUANT, h, w)
+    assert abs(p - qres["psnr"]) <= PSNR_TOL
+
+
 @pytest.mark.parametrize("pitch_extra,offset", [(8, 0), (3, 1), (0, 2)])
 def test_compress_eval_quant_recon_layouts(pitch_extra, offset):
     # Whole-block plane (reconstruction staged through LDS), a short last chunk
