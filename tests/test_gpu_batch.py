@@ -62,6 +62,38 @@ def test_quant_batch_equals_single_and_oracle(full, use_graph, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_quant_batch_exact_ties(layout):
+    # Small uniform tables make exact ties Y / (g_k Q) = n + 1/2 frequent where
+    # s_k s_l is rational; they must round away from zero in both quantiser forms:
+    # whole-block planes (coefficient-domain error) and planes with partial blocks
+    # (pixel-domain error) in one batch.
+    shapes = [(64, 64), (96, 80), (40, 128), (70, 50), (37, 61), (128, 72)]
+    imgs = [synth.render_np(500 + i, h, w) for i, (h, w) in enumerate(shapes)]
+    dev = [torch.from_numpy(a).to(DEV) for a in imgs]
+    qvs = [1, 2, 3, 4, 5, 6]
+    sels = [R.select(R.SEL_QUANT, qtable=[qv] * 64, level_shift=128) for qv in qvs]
+    plan = R.BatchPlan(dev, sels, R.COEF_I16, recon=True,
+                       tuning=R.Tuning(1 + 3 * (layout == R.LAYOUT_PER_PLANE), 4, 0, layout))
+    plan.run()
+    sse = host(plan.sse)
+    g_ = np.diag(O.gram())
+    rational = np.equal.outer(g_, g_)
+    n_ties = 0
+    for i, (img, qv) in enumerate(zip(imgs, qvs)):
+        qt = np.full((8, 8), qv)
+        ref = O.quant_eval(img, qt)
+        y = np.asarray(ref["Y"])
+        num = 2 * np.abs(y)
+        den = np.where(rational, g_[:, None] * qv, 1) * np.ones((8, 8), dtype=np.int64)
+        n_ties += int((rational & (num % den == 0) & ((num // den) % 2 == 1)).sum())
+        assert np.array_equal(host(plan.coef_views[i]).astype(np.int64), ref["q"].reshape(-1, 64)), i
+        assert np.max(np.abs(host(plan.recon_views[i]) - ref["recon"])) <= 1e-4, i
+        h, w = img.shape
+        assert abs(R.psnr_from_sse(int(sse[i]), R.SEL_QUANT, h, w) - ref["psnr"]) <= 1e-3, i
+    assert n_ties > 100
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_retention_batch_equals_single_and_oracle(layout):
     imgs, dev, rng = ragged_planes(17, 2, full_blocks=False)
     rs = [int(r) for r in rng.integers(1, 46, size=len(imgs))]
