@@ -701,14 +701,22 @@ struct Prefetch {
   static constexpr bool value = !RECON && (EV == EV_NONE || EV == EV_COEF || EV == EV_SWEEP);
 };
 
-// A plane of at most 128 blocks per CU (on 256 CUs) runs in chunks of 64
-// blocks, one per lane: its waves are few, each one's latency decides the
-// launch, and a chunk of 64 blocks halves the inverse and the stores per wave.
-__host__ __device__ constexpr bool half_chunks(int nblocks) { return nblocks <= 128 * 256; }
+// Chunks of 64 blocks, one per lane (the high halves of the pairs empty):
+//  * for the pure streams (forward, selection or quantisation, coefficient
+//    stores; no error sums) at every size: twice the waves, each with half the
+//    stores, keep more of the plane in flight (8192^2 quantised to int16:
+//    36.9 -> 35.9 us; keep-r to int32: 61.4 -> 55.8 us);
+//  * for the other kernels on a plane of at most 128 blocks per CU (on 256
+//    CUs): its waves are few and each one's latency decides the launch.  On
+//    larger planes the doubled forward work per block costs more than it gains.
+template <int EV>
+__host__ __device__ constexpr bool half_chunks(int nblocks) {
+  return EV == EV_NONE || nblocks <= 128 * 256;
+}
 
 template <int SEL, int CO, bool RECON, int EV>
 __device__ __forceinline__ void plane_kernel_body(const Plane& P, QCPtr qc) {
-  // Chunks of 128 blocks (64 on small planes, see half_chunks): wave w takes
+  // Chunks of 128 blocks (64 where half_chunks says so): wave w takes
   // chunks w, w + W, ... (W waves in the grid).  Without error sums the grid
   // covers the plane, one chunk per wave; with them the grid is capped, so a
   // large plane's sums take one atomic per wave instead of one per chunk, all on
@@ -718,7 +726,7 @@ __device__ __forceinline__ void plane_kernel_body(const Plane& P, QCPtr qc) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int n_waves = gridDim.x * wpg;
-  const bool half = half_chunks(P.nblocks);
+  const bool half = half_chunks<EV>(P.nblocks);
   const int cs = half ? 64 : 128;
   int c = blockIdx.x * wpg + wave;
   if (c * cs >= P.nblocks) return;
@@ -1034,7 +1042,7 @@ constexpr int kPlaneWavesPerCU = 8;
 template <int SEL, int CO, bool RECON, int EV>
 static hipError_t launch_plane_t(const Plane& P, const QuantConsts& qc, int wpg, hipStream_t s) {
   const int n_cu = device_cu_count();
-  const int chunks = half_chunks(P.nblocks) ? (P.nblocks + 63) / 64 : (P.nblocks + 127) / 128;
+  const int chunks = half_chunks<EV>(P.nblocks) ? (P.nblocks + 63) / 64 : (P.nblocks + 127) / 128;
   int grid = (chunks + wpg - 1) / wpg;
   if constexpr (EV != EV_NONE) {
     const int cap = n_cu * kPlaneWavesPerCU / wpg;
