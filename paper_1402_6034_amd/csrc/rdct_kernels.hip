@@ -491,8 +491,8 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t s) {
 // Pixels of one chunk as loaded by a lane: blocks t0 + lane (lo) and
 // t0 + 64 + lane (hi).
 // With `half`, the chunk is blocks t0 .. t0 + 63 only (the high blocks of the
-// pairs stay empty): a small plane then spreads over twice the waves.  nv0 / nv1
-// count the blocks of each half inside the plane (wave-uniform).
+// pairs stay empty; see half_chunks).  nv0 / nv1 count the blocks of each half
+// inside the plane (wave-uniform).
 struct Pixels {
   uint32_t al[16], ah[16];
   int xl, yl, xh, yh;
@@ -557,7 +557,7 @@ __device__ __forceinline__ uint64_t plane_chunk(const Plane& P, QCPtr qc, const 
     // Quantise one block of the pair at a time through the lane's stage slot.
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      if ((h ? px.nv1 : px.nv0) == 0) continue;  // an empty half (small planes)
+      if ((h ? px.nv1 : px.nv0) == 0) continue;  // an empty half (64-block chunks)
       QErr e;
       quant_rows<CO, ERR, WB, FQ>(v, h, qc_after_s(qc, h), my_stage, e);
       if constexpr (ERR) {
