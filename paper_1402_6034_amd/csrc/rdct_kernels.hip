@@ -704,8 +704,8 @@ struct Prefetch {
 // Chunks of 64 blocks, one per lane (the high halves of the pairs empty):
 //  * for the pure streams (forward, selection or quantisation, coefficient
 //    stores; no error sums) at every size: twice the waves, each with half the
-//    stores, keep more of the plane in flight (8192^2 quantised to int16:
-//    36.9 -> 35.9 us; keep-r to int32: 61.4 -> 55.8 us);
+//    stores, keep more of the plane in flight (8192^2 quantised to int16,
+//    input and output rotating past the last-level cache: 37.6 -> 36.4 us);
 //  * for the other kernels on a plane of at most 128 blocks per CU (on 256
 //    CUs): its waves are few and each one's latency decides the launch.  On
 //    larger planes the doubled forward work per block costs more than it gains.
