@@ -1,6 +1,8 @@
 """The largest planes each entry point accepts, checked by properties that hold
 at any size (and, for the codec, by sampled blocks against the oracle):
 
+  * rdct_forward        2^26 blocks (65536 x 65536, the limit; 2^20 waves of
+    64-block chunks): sampled blocks, the first and the last, match the oracle;
   * rdct_compress_eval  5,997,601 blocks (19592 x 19592; the limit is 6,000,000):
     the whole plane's error sums equal the sums over four bands taken alone,
     for the 45-value retention sweep and for quantisation;
@@ -31,6 +33,25 @@ def host(t):
 
 def raw(t):
     return host(t).astype(np.int64)
+
+
+def test_forward_largest_plane():
+    # The 8192^2 synthetic plane tiled 8 x 8 times: block (by, bx) of the large
+    # plane is block (by % 1024, bx % 1024) of the small one.
+    base = synth.render(9, 8192, 8192, device=DEV)
+    img = base.repeat(8, 8)
+    nbx = 65536 // 8
+    assert nbx * nbx == 1 << 26
+    coef = R.forward(img, R.select(R.SEL_QUANT, quality=50, level_shift=128), R.COEF_I16)
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([[0, nbx - 1, nbx, (1 << 26) - 1],
+                                    rng.integers(0, 1 << 26, size=400)]))
+    got = raw(coef[torch.from_numpy(idx).to(DEV)])
+    small = (idx // nbx % 1024) * 1024 + (idx % nbx % 1024)
+    want = O.quantize(O.forward_blocks(O.sample_blocks(host(base), small), 128), O.quant_table(50))
+    assert np.array_equal(got, np.asarray(want).reshape(-1, 64))
+    del img, coef, base
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("mode", ["sweep", "quant"])
